@@ -1,0 +1,130 @@
+/*
+ * ccmf.h -- C ABI of the MI355X solver for the effective crack energy on a
+ * combinatorially consistent grid (Ernesti & Schneider, arXiv 2103.05968).
+ *
+ * The library computes, for a periodic voxel field gamma >= 0 of crack
+ * resistances and a prescribed mean crack normal xibar, the CCMF
+ * discretization of the effective crack energy
+ *
+ *     geff(xibar) = min { (1/N) sum_x gamma[x] |xi[x]| : xi in K_xibar }
+ *                 = max { <xibar, v> : div^- v = 0, |A v| <= gamma }
+ *
+ * (Sec. 3.1, eq:CCMF_FFT_problem_primal_final and eq:CCMF_FFT_problemA) with the
+ * damped ADMM of Sec. 3.2 (eq:CCMF_FFT_ADMM, second form): each iteration solves
+ * the periodic discrete Laplacian div^- grad^+ in a separable spectral basis for
+ * the node potential, projects each voxel's six incident edge quantities onto
+ * the ball of radius gamma, updates the multiplier and reduces (in FP64) the
+ * residual, energy and penalty statistics that drive the adaptive penalty.
+ * All steps run in HIP kernels on the device; the host only launches them and
+ * polls a convergence flag.
+ *
+ * Conventions for every entry point:
+ *  - Fields are C-order [N1][N2][N3] (k = third index fastest), one contiguous
+ *    block per field; vector fields are component-major [c][N1][N2][N3].
+ *  - "device" pointers are HIP device allocations on the device that was
+ *    current at ccmf_setup; "host" pointers are ordinary host memory.
+ *  - Element type of device fields is the plan's dtype (double for CCMF_F64,
+ *    float for CCMF_F32).  Scalars crossing the ABI are always double.
+ *  - Every call is ordered on the stream given to ccmf_setup; calls returning
+ *    host results synchronize that stream before returning.
+ *  - The caller owns every pointer it passes; the plan copies what it keeps
+ *    (kappa) and never retains a caller pointer past the call.
+ *  - Return value 0 = success; negative = error (nothing written to outputs,
+ *    message in ccmf_last_error()); CCMF_NOT_CONVERGED (= 1) is a warning:
+ *    all outputs are written from the last iterate.
+ *  - A plan is not thread safe; distinct plans are independent.
+ */
+#ifndef CCMF_H_
+#define CCMF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ccmf_plan_s* ccmf_plan;
+
+enum {
+  CCMF_OK = 0,
+  CCMF_NOT_CONVERGED = 1, /* max_iter reached; outputs hold the last iterate  */
+  CCMF_EINVAL = -1,       /* invalid argument (message says which)             */
+  CCMF_ENOMEM = -2,       /* device or pinned-host allocation failed           */
+  CCMF_EDEVICE = -3,      /* a HIP call failed (HIP error text in the message) */
+  CCMF_ESTATE = -4        /* call out of order (e.g. outputs before a solve)   */
+};
+
+enum { CCMF_F64 = 0, CCMF_F32 = 1 };
+
+/* Penalty rules of Sec. 3.2: Barzilai-Borwein, constant rho0, Lorenz-Tran-Dinh. */
+enum { CCMF_RHO_BB = 0, CCMF_RHO_CONST = 1, CCMF_RHO_LTD = 2 };
+
+typedef struct {
+  double delta;        /* damping of eq:CCMF_FFT_ADMM, in (0,1); 0 selects 0.25 (Sec. 4.1)  */
+  double rho0;         /* initial penalty; 0 selects the smallest positive kappa of the field */
+  int32_t rule;        /* CCMF_RHO_*                                                          */
+  int32_t max_iter;    /* maximum number of xi-steps; 0 selects 20000                         */
+  int32_t check_every; /* host polls the device convergence flags every this many
+                          iterations (the kernels stop by themselves); 0 selects 32          */
+  int32_t time_kernels;/* nonzero: time every launch of the fused update kernel with HIP
+                          events on the plan's stream (read with ccmf_kernel_times)         */
+} ccmf_options;
+
+/* Create a plan for n_fields crack-resistance fields of size dims[0] x dims[1] x
+ * dims[2] (each >= 1, N = product < 2^31, each dim <= 2048 in F64 / 4096 in F32).
+ * kappa_dev: device, [n_fields][N1][N2][N3] of the plan's dtype, finite and >= 0
+ * (zeros are pores).  Copied into the plan.  stream: hipStream_t (NULL = default).
+ * Errors: CCMF_EINVAL for bad sizes/dtype or a negative / non-finite kappa entry. */
+int ccmf_setup(ccmf_plan* out, const int64_t dims[3], int64_t n_fields, int32_t dtype,
+               const void* kappa_dev, void* stream);
+
+/* Solve the damped ADMM of Sec. 3.2 for every (field f, load l) pair, problem
+ * index b = f * n_loads + l, all in one batched launch sequence; every problem
+ * stops by itself when |e^k - xi^{k+1/2}|_{L2} <= tol |<v^k>| (eq:convergence_criterion).
+ * xi:        host, [n_loads][3] load directions (normalised to unit length).
+ * tol:       > 0.   opt: host, may be NULL (all defaults).
+ * geff:      host out, [B]: primal energy (1/N) sum gamma |xi^{k+1/2}| at the stopping iterate.
+ * iters:     host out, [B]: number of xi-steps taken.  residual: host out, [B] (nullable).
+ * dual_est:  host out, [B]: <A xibar, v^k> (nullable).
+ * phi_dev:   device out, [B][N] node potential of the stopping iterate, zero mean (nullable).
+ * flux_dev:  device out, [B][3][N] face fluxes A* v^k, v_c[x] on face x + e_c/2 (nullable).
+ * The solution state stays in the plan for ccmf_grad_kappa until the next solve. */
+int ccmf_solve(ccmf_plan p, const double* xi, int64_t n_loads, double tol, const ccmf_options* opt,
+               double* geff, int32_t* iters, double* residual, double* dual_est,
+               void* phi_dev, void* flux_dev);
+
+/* Envelope-theorem gradient of the last solve (not in the paper; Danskin's theorem
+ * applied to the min-cut form eq:CCMF_FFT_problem_primal_final, linear in gamma):
+ *   dkappa[f][x] = sum_l dL_dgeff[f*n_loads + l] * |xi^{k+1/2}_{f,l}[x]| / N.
+ * dL_dgeff: host, [B].  dkappa_dev: device out, [n_fields][N] of the plan's dtype. */
+int ccmf_grad_kappa(ccmf_plan p, const double* dL_dgeff, void* dkappa_dev);
+
+/* Average device duration (ms) of the fused update kernel over the launches timed
+ * since the last call (options.time_kernels), the number of launches, and the
+ * kernel's algorithmic HBM bytes per launch per problem.  Resets the counters. */
+int ccmf_kernel_times(ccmf_plan p, double* avg_ms, int64_t* count, double* bytes_per_launch);
+
+/* Apply the spectral solve phi = (div^- grad^+)^dagger r (the pseudo-inverse in
+ * eq:CCMF_FFT_Gamma_2) to `count` fields with the plan's transform kernels.
+ * r_dev, phi_dev: device, [count][N] of the plan's dtype (may alias). */
+int ccmf_laplace_pinv(ccmf_plan p, const void* r_dev, void* phi_dev, int64_t count);
+
+/* One separable Hartley transform pass along `axis` (0, 1, 2) of `count` fields,
+ * in place: H[q] = sum_t x[t] (cos + sin)(2 pi q t / n), unnormalised.
+ * data_dev: device, [count][N] of the plan's dtype.  A diagnostic of the spectral solve. */
+int ccmf_hartley_axis(ccmf_plan p, void* data_dev, int64_t count, int32_t axis);
+
+/* Plain device copy of nbytes (a multiple of 16) with a streaming kernel on
+ * `stream`: the bandwidth reference used to calibrate traffic counters. */
+int ccmf_stream_copy(void* dst_dev, const void* src_dev, int64_t nbytes, void* stream);
+
+void ccmf_destroy(ccmf_plan p);
+
+/* Message for the last non-zero status returned on the calling thread. */
+const char* ccmf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCMF_H_ */

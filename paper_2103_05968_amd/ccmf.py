@@ -1,0 +1,183 @@
+"""Python binding of the CCMF solver library (include/ccmf.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream; there is no fallback
+path -- if the library is not built, importing or calling this raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+__all__ = ["Plan", "SolveResult", "effective_crack_energy", "GeffFunction", "stream_copy"]
+
+_DT = {torch.float64: _lib.CCMF_F64, torch.float32: _lib.CCMF_F32}
+
+
+@dataclass
+class SolveResult:
+    geff: np.ndarray            # [F, L] effective crack energy per field and load
+    iterations: np.ndarray      # [F, L] number of xi-steps taken
+    residual: np.ndarray        # [F, L] |e^k - xi^{k+1/2}|_{L2} at the stopping iterate
+    dual_est: np.ndarray        # [F, L] <A xibar, v^k>
+    converged: bool
+    phi: Optional[torch.Tensor] = None    # [F, L, N1, N2, N3]
+    flux: Optional[torch.Tensor] = None   # [F, L, 3, N1, N2, N3]
+
+
+def _dptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A solver plan for F crack-resistance fields kappa of one grid size.
+
+    kappa: CUDA tensor [N1, N2, N3] or [F, N1, N2, N3], float64 (FP64 mode) or
+    float32 (FP32 fields, FP64 reductions).  The plan copies it.
+    """
+
+    def __init__(self, kappa: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+        lib = _lib.load()
+        if not kappa.is_cuda:
+            raise ValueError("kappa must be a CUDA (HIP) tensor")
+        if kappa.dtype not in _DT:
+            raise ValueError("kappa must be float32 or float64")
+        if kappa.dim() == 3:
+            kappa = kappa.unsqueeze(0)
+        if kappa.dim() != 4:
+            raise ValueError("kappa must have shape [N1,N2,N3] or [F,N1,N2,N3]")
+        kappa = kappa.contiguous()
+        self.dtype = kappa.dtype
+        self.device = kappa.device
+        self.n_fields = int(kappa.shape[0])
+        self.dims = tuple(int(d) for d in kappa.shape[1:])
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        dims = (ctypes.c_int64 * 3)(*self.dims)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(lib.ccmf_setup(ctypes.byref(handle), dims, self.n_fields, _DT[self.dtype],
+                                      _dptr(kappa), ctypes.c_void_p(self.stream.cuda_stream)))
+        self._h = handle
+        self._lib = lib
+        self.n_loads = 0
+
+    @property
+    def N(self) -> int:
+        return self.dims[0] * self.dims[1] * self.dims[2]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ccmf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, xi: Sequence[Sequence[float]], tol: float = 1e-4, *, delta: float = 0.25,
+              rule: str = "bb", rho0: float = 0.0, max_iter: int = 20000, check_every: int = 32,
+              want_phi: bool = False, want_flux: bool = False, time_kernels: bool = False,
+              raise_not_converged: bool = False) -> SolveResult:
+        xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(-1, 3))
+        L = xi.shape[0]
+        B = self.n_fields * L
+        opt = _lib.Options(delta=delta, rho0=rho0, rule=_lib.RULES[rule], max_iter=max_iter,
+                           check_every=check_every, time_kernels=int(bool(time_kernels)))
+        geff = np.zeros(B)
+        iters = np.zeros(B, dtype=np.int32)
+        res = np.zeros(B)
+        dual = np.zeros(B)
+        phi = flux = None
+        if want_phi:
+            phi = torch.empty((self.n_fields, L) + self.dims, dtype=self.dtype, device=self.device)
+        if want_flux:
+            flux = torch.empty((self.n_fields, L, 3) + self.dims, dtype=self.dtype, device=self.device)
+        dp = ctypes.POINTER(ctypes.c_double)
+        with torch.cuda.device(self.device):
+            code = self._lib.ccmf_solve(
+                self._h, xi.ctypes.data_as(dp), L, float(tol), ctypes.byref(opt),
+                geff.ctypes.data_as(dp), iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                res.ctypes.data_as(dp), dual.ctypes.data_as(dp),
+                _dptr(phi) if phi is not None else None, _dptr(flux) if flux is not None else None)
+        _lib.check(code, allow_not_converged=not raise_not_converged)
+        self.n_loads = L
+        shape = (self.n_fields, L)
+        return SolveResult(geff.reshape(shape), iters.reshape(shape), res.reshape(shape),
+                           dual.reshape(shape), code == _lib.CCMF_OK, phi, flux)
+
+    def grad_kappa(self, dL_dgeff) -> torch.Tensor:
+        """Envelope gradient of the last solve: sum_l dL/dgeff[f,l] * |xi*_{f,l}[x]|/N."""
+        dl = np.ascontiguousarray(np.asarray(dL_dgeff, dtype=np.float64).reshape(-1))
+        if dl.size != self.n_fields * self.n_loads:
+            raise ValueError("dL_dgeff must have one entry per (field, load) of the last solve")
+        out = torch.empty((self.n_fields,) + self.dims, dtype=self.dtype, device=self.device)
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.ccmf_grad_kappa(self._h, dl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 _dptr(out)))
+        return out
+
+    def kernel_times(self):
+        """(average ms, launches, algorithmic bytes per launch and problem) of the fused update kernel."""
+        avg = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        by = ctypes.c_double()
+        _lib.check(self._lib.ccmf_kernel_times(self._h, ctypes.byref(avg), ctypes.byref(cnt), ctypes.byref(by)))
+        return avg.value, cnt.value, by.value
+
+    def laplace_pinv(self, r: torch.Tensor) -> torch.Tensor:
+        """(div^- grad^+)^dagger applied to each field of r [..., N1, N2, N3]."""
+        r = r.to(self.dtype).contiguous()
+        out = torch.empty_like(r)
+        count = r.numel() // self.N
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.ccmf_laplace_pinv(self._h, _dptr(r), _dptr(out), count))
+        return out
+
+    def hartley_axis(self, data: torch.Tensor, axis: int) -> torch.Tensor:
+        """Unnormalised Hartley transform along one axis of each field (in place on a copy)."""
+        out = data.to(self.dtype).contiguous().clone()
+        count = out.numel() // self.N
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.ccmf_hartley_axis(self._h, _dptr(out), count, int(axis)))
+        return out
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+    lib = _lib.load()
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    nbytes = src.numel() * src.element_size()
+    _lib.check(lib.ccmf_stream_copy(_dptr(dst), _dptr(src), nbytes, ctypes.c_void_p(s.cuda_stream)))
+
+
+class GeffFunction(torch.autograd.Function):
+    """geff(kappa) for fixed loads, differentiable in kappa by the envelope theorem."""
+
+    @staticmethod
+    def forward(ctx, kappa, xi, tol, solve_kwargs):
+        plan = Plan(kappa.detach())
+        res = plan.solve(xi, tol, **(solve_kwargs or {}))
+        ctx.plan = plan
+        ctx.kappa_shape = kappa.shape
+        return torch.as_tensor(res.geff, dtype=torch.float64, device=kappa.device).reshape(
+            (plan.n_fields, -1) if kappa.dim() == 4 else (-1,))
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        plan = ctx.plan
+        g = plan.grad_kappa(grad_out.detach().double().cpu().numpy())
+        plan.close()
+        return g.reshape(ctx.kappa_shape), None, None, None
+
+
+def effective_crack_energy(kappa: torch.Tensor, xi, tol: float = 1e-4, **solve_kwargs) -> torch.Tensor:
+    """Differentiable geff(kappa; xi) (float64 result, one value per field and load)."""
+    return GeffFunction.apply(kappa, xi, tol, solve_kwargs)

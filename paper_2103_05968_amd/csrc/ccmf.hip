@@ -1,0 +1,605 @@
+// Host runtime of the CCMF solver: plan, buffers, launch sequence, C ABI.
+// Kernels: ccmf_kernels.h (stencil, fused update, reductions), ccmf_dht.h
+// (spectral Laplacian solve).  See include/ccmf.h for the interface contract.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ccmf.h"
+#include "ccmf_dht.h"
+#include "ccmf_kernels.h"
+
+using namespace ccmf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? CCMF_ENOMEM : CCMF_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+#define HIP_LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+struct Axis {
+  int n = 1;
+  std::vector<int> radix;
+  void* tw = nullptr;  // complex twiddles exp(-2 pi i t / n), t < n (plan dtype)
+  void* s = nullptr;   // 4 sin^2(pi q / n), q < n (plan dtype)
+};
+
+std::vector<int> factor_radices(int n) {
+  std::vector<int> r;
+  int m = n;
+  while (m % 8 == 0 && m > 4) {
+    r.push_back(8);
+    m /= 8;
+  }
+  if (m % 4 == 0) {
+    r.push_back(4);
+    m /= 4;
+  }
+  if (m % 2 == 0) {
+    r.push_back(2);
+    m /= 2;
+  }
+  for (int p = 3; m > 1; p += 2) {
+    while (m % p == 0) {
+      r.push_back(p);
+      m /= p;
+    }
+    if (p * p > m && m > 1) {
+      r.push_back(m);
+      m = 1;
+    }
+  }
+  return r;
+}
+
+}  // namespace
+
+struct ccmf_plan_s {
+  int dt = CCMF_F64;
+  size_t esz = 8;
+  int n[3] = {1, 1, 1};
+  uint32_t N = 1;
+  int64_t nfields = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* kap = nullptr;
+  std::vector<double> kmin, kmax;  // per field: smallest positive, largest
+  Axis ax[3];
+
+  // solve state
+  int64_t B = 0, nloads = 0;
+  void* z[2] = {nullptr, nullptr};
+  void* a[2] = {nullptr, nullptr};
+  void* r = nullptr;
+  double* partials = nullptr;
+  int nparts = 0;
+  Prob* prob = nullptr;    // device
+  Prob* probh = nullptr;   // pinned host
+  bool solved = false;
+  int upd_blocks = 0, tiles_per_blk = 0;
+
+  // kernel timing
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double kt_sum = 0.0;
+  int64_t kt_count = 0;
+
+  ~ccmf_plan_s() {
+    hipFree(kap);
+    for (int c = 0; c < 3; ++c) {
+      hipFree(ax[c].tw);
+      hipFree(ax[c].s);
+    }
+    free_state();
+    for (auto e : ev) hipEventDestroy(e);
+  }
+  void free_state() {
+    for (int p = 0; p < 2; ++p) {
+      hipFree(z[p]);
+      hipFree(a[p]);
+      z[p] = a[p] = nullptr;
+    }
+    hipFree(r);
+    hipFree(partials);
+    hipFree(prob);
+    if (probh) hipHostFree(probh);
+    r = nullptr;
+    partials = nullptr;
+    prob = nullptr;
+    probh = nullptr;
+    B = 0;
+  }
+};
+
+namespace {
+
+Geo make_geo(const ccmf_plan_s* p) {
+  Geo g;
+  g.n1 = p->n[0];
+  g.n2 = p->n[1];
+  g.n3 = p->n[2];
+  g.n23 = p->n[1] * p->n[2];
+  g.N = p->N;
+  g.nloads = (int32_t)p->nloads;
+  g.tiles = (int32_t)((p->N + kThreads - 1) / kThreads);
+  g.tiles_per_blk = p->tiles_per_blk;
+  return g;
+}
+
+template <typename T>
+int upload_axis(Axis& ax, int n) {
+  ax.n = n;
+  ax.radix = factor_radices(n);
+  std::vector<T> tw(2 * (size_t)n), s(n);
+  for (int t = 0; t < n; ++t) {
+    // angles reduced exactly in integer arithmetic, evaluated in long double
+    const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)n;
+    tw[2 * t] = (T)cosl(ang);
+    tw[2 * t + 1] = (T)sinl(ang);
+    const long double sv = sinl(3.14159265358979323846264338327950288L * (long double)t / (long double)n);
+    s[t] = (T)(4.0L * sv * sv);
+  }
+  HIP_TRY(hipMalloc(&ax.tw, tw.size() * sizeof(T)));
+  HIP_TRY(hipMalloc(&ax.s, s.size() * sizeof(T)));
+  HIP_TRY(hipMemcpy(ax.tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ax.s, s.data(), s.size() * sizeof(T), hipMemcpyHostToDevice));
+  return CCMF_OK;
+}
+
+// lines per LDS tile: ping-pong complex buffers within 64 KiB
+int lines_per_tile(int n, size_t esz, int lines_total) {
+  int nl = 32;
+  while (nl > 2 && (size_t)2 * nl * n * esz > 65536) nl >>= 1;
+  if (lines_total < nl) nl = std::max(2, lines_total + (lines_total & 1));
+  return nl;
+}
+
+// Launch one Hartley pass along `axis` over `count` fields of `data`.
+template <typename T>
+int launch_hartley(ccmf_plan_s* p, T* data, int64_t count, int axis, bool middle, const Prob* prob) {
+  const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
+  const Axis& ax = p->ax[axis];
+  DhtArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.n = ax.n;
+  A.nstages = (int)ax.radix.size();
+  if (A.nstages > kMaxStages) return fail(CCMF_EINVAL, "transform length %d has too many factors", ax.n);
+  for (int i = 0; i < A.nstages; ++i) A.radix[i] = ax.radix[i];
+  A.field_stride = p->N;
+  A.scale = 1.0 / (double)p->N;
+  A.n2 = n2;
+  A.n3 = n3;
+  int outers;
+  bool contig;
+  if (axis == 2) {  // rows along k, contiguous samples
+    contig = true;
+    A.lines_total = n1 * n2;
+    A.ss = 1;
+    A.ls = n3;
+    A.os = 0;
+    outers = 1;
+  } else if (axis == 1) {
+    contig = false;
+    A.lines_total = n3;
+    A.ss = n3;
+    A.ls = 1;
+    A.os = (int64_t)n2 * n3;
+    outers = n1;
+  } else {
+    contig = false;
+    A.lines_total = n3;
+    A.ss = (int64_t)n2 * n3;
+    A.ls = 1;
+    A.os = n3;
+    outers = n2;
+  }
+  A.nl = lines_per_tile(A.n, sizeof(T), A.lines_total);
+  A.tiles_per_outer = (A.lines_total + A.nl - 1) / A.nl;
+  const size_t lds = (size_t)2 * A.nl * A.n * sizeof(T);
+  if (lds > 65536) return fail(CCMF_EINVAL, "transform length %d too large for the LDS tile", A.n);
+  dim3 grid((unsigned)(outers * A.tiles_per_outer), (unsigned)count);
+  const C2<T>* tw = reinterpret_cast<const C2<T>*>(ax.tw);
+  const T* s1 = reinterpret_cast<const T*>(p->ax[0].s);
+  const T* s2 = reinterpret_cast<const T*>(p->ax[1].s);
+  const T* s3 = reinterpret_cast<const T*>(p->ax[2].s);
+  if (middle) {
+    hipLaunchKernelGGL((k_hartley<T, false, true>), grid, dim3(kThreads), lds, p->stream, data, tw, A,
+                       s1, s2, s3, prob);
+  } else if (contig) {
+    hipLaunchKernelGGL((k_hartley<T, true, false>), grid, dim3(kThreads), lds, p->stream, data, tw, A,
+                       s1, s2, s3, prob);
+  } else {
+    hipLaunchKernelGGL((k_hartley<T, false, false>), grid, dim3(kThreads), lds, p->stream, data, tw, A,
+                       s1, s2, s3, prob);
+  }
+  HIP_LAUNCH_CHECK();
+  return CCMF_OK;
+}
+
+// phi = (div^- grad^+)^dagger r in place: k, j, [i, scale, i], j, k
+template <typename T>
+int launch_laplace(ccmf_plan_s* p, T* data, int64_t count, const Prob* prob) {
+  int rc;
+  if (p->n[2] > 1 && (rc = launch_hartley<T>(p, data, count, 2, false, prob))) return rc;
+  if (p->n[1] > 1 && (rc = launch_hartley<T>(p, data, count, 1, false, prob))) return rc;
+  if ((rc = launch_hartley<T>(p, data, count, 0, true, prob))) return rc;
+  if (p->n[1] > 1 && (rc = launch_hartley<T>(p, data, count, 1, false, prob))) return rc;
+  if (p->n[2] > 1 && (rc = launch_hartley<T>(p, data, count, 2, false, prob))) return rc;
+  return CCMF_OK;
+}
+
+template <typename T>
+int kappa_stats(ccmf_plan_s* p) {
+  const int blocks = (int)std::min<uint64_t>(1024, (p->N + kThreads - 1) / kThreads);
+  double* d = nullptr;
+  const size_t cnt = (size_t)p->nfields * blocks * 3;
+  HIP_TRY(hipMalloc(&d, cnt * sizeof(double)));
+  hipLaunchKernelGGL((k_kappa_stats<T>), dim3(blocks, (unsigned)p->nfields), dim3(kThreads), 0, p->stream,
+                     reinterpret_cast<const T*>(p->kap), p->N, d);
+  hipError_t e = hipGetLastError();
+  std::vector<double> h(cnt);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, cnt * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  hipFree(d);
+  if (e != hipSuccess) return fail(CCMF_EDEVICE, "kappa statistics: %s", hipGetErrorString(e));
+  p->kmin.assign(p->nfields, INFINITY);
+  p->kmax.assign(p->nfields, 0.0);
+  for (int64_t f = 0; f < p->nfields; ++f) {
+    double bad = 0.0;
+    for (int bl = 0; bl < blocks; ++bl) {
+      const double* o = &h[((size_t)f * blocks + bl) * 3];
+      p->kmin[f] = std::min(p->kmin[f], o[0]);
+      p->kmax[f] = std::max(p->kmax[f], o[1]);
+      bad += o[2];
+    }
+    if (bad > 0.0)
+      return fail(CCMF_EINVAL, "kappa field %lld has %.0f negative or non-finite entries", (long long)f, bad);
+  }
+  return CCMF_OK;
+}
+
+int ensure_state(ccmf_plan_s* p, int64_t nloads) {
+  const int64_t B = p->nfields * nloads;
+  p->nloads = nloads;
+  // fused update: up to 2048 blocks per problem, independent of the batch size,
+  // so the FP64 reduction order (and every result) is the same batched or alone
+  const int tiles = (int)((p->N + kThreads - 1) / kThreads);
+  int want = std::min(tiles, 2048);
+  if (want > 8) want &= ~7;
+  p->tiles_per_blk = (tiles + want - 1) / want;
+  p->upd_blocks = (tiles + p->tiles_per_blk - 1) / p->tiles_per_blk;
+  if (B == p->B && p->z[0] != nullptr) return CCMF_OK;
+  p->free_state();
+  const size_t N = p->N;
+  for (int q = 0; q < 2; ++q) {
+    HIP_TRY(hipMalloc(&p->z[q], (size_t)B * 6 * N * p->esz));
+    HIP_TRY(hipMalloc(&p->a[q], (size_t)B * N * p->esz));
+  }
+  HIP_TRY(hipMalloc(&p->r, (size_t)B * N * p->esz));
+  HIP_TRY(hipMalloc(&p->partials, (size_t)B * p->upd_blocks * kNQ * sizeof(double)));
+  HIP_TRY(hipMalloc(&p->prob, (size_t)B * sizeof(Prob)));
+  HIP_TRY(hipHostMalloc((void**)&p->probh, (size_t)B * sizeof(Prob), hipHostMallocDefault));
+  p->B = B;
+  return CCMF_OK;
+}
+
+int record_event(ccmf_plan_s* p, hipEvent_t* out) {
+  if (p->ev_used == p->ev.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    p->ev.push_back(e);
+  }
+  *out = p->ev[p->ev_used++];
+  HIP_TRY(hipEventRecord(*out, p->stream));
+  return CCMF_OK;
+}
+
+int harvest_events(ccmf_plan_s* p) {
+  if (p->ev_used == 0) return CCMF_OK;
+  HIP_TRY(hipEventSynchronize(p->ev[p->ev_used - 1]));
+  for (size_t i = 0; i + 1 < p->ev_used; i += 2) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
+    p->kt_sum += ms;
+    p->kt_count += 1;
+  }
+  p->ev_used = 0;
+  return CCMF_OK;
+}
+
+template <typename T>
+int run_iteration(ccmf_plan_s* p, int it, bool timed) {
+  const Geo g = make_geo(p);
+  const int cur = it & 1, nxt = cur ^ 1;
+  T* z0 = reinterpret_cast<T*>(p->z[cur]);
+  T* a0 = reinterpret_cast<T*>(p->a[cur]);
+  T* z1 = reinterpret_cast<T*>(p->z[nxt]);
+  T* a1 = reinterpret_cast<T*>(p->a[nxt]);
+  T* r = reinterpret_cast<T*>(p->r);
+  const T* kap = reinterpret_cast<const T*>(p->kap);
+  dim3 grid((unsigned)p->upd_blocks, (unsigned)p->B);
+  hipLaunchKernelGGL((k_div<T>), grid, dim3(kThreads), 0, p->stream, g, z0, a0, r, p->prob);
+  HIP_LAUNCH_CHECK();
+  int rc = launch_laplace<T>(p, r, p->B, p->prob);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  if (timed && (rc = record_event(p, &e0))) return rc;
+  hipLaunchKernelGGL((k_update<T>), grid, dim3(kThreads), 0, p->stream, g, kap, z0, a0, r, z1, a1,
+                     p->partials, p->prob);
+  HIP_LAUNCH_CHECK();
+  if (timed && (rc = record_event(p, &e1))) return rc;
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)p->B), dim3(kThreads), 0, p->stream, it, p->N,
+                     p->upd_blocks, p->partials, p->prob, (double*)nullptr, 0);
+  HIP_LAUNCH_CHECK();
+  return CCMF_OK;
+}
+
+template <typename T>
+int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, const ccmf_options* o,
+               double* geff, int32_t* iters, double* residual, double* dual_est, void* phi_dev,
+               void* flux_dev) {
+  ccmf_options opt;
+  std::memset(&opt, 0, sizeof(opt));
+  if (o) opt = *o;
+  if (opt.delta == 0.0) opt.delta = 0.25;
+  if (opt.max_iter == 0) opt.max_iter = 20000;
+  if (opt.check_every == 0) opt.check_every = 32;
+  if (!(opt.delta > 0.0 && opt.delta < 1.0)) return fail(CCMF_EINVAL, "delta must lie in (0,1)");
+  if (opt.max_iter < 1) return fail(CCMF_EINVAL, "max_iter must be >= 1");
+  if (opt.check_every < 1) return fail(CCMF_EINVAL, "check_every must be >= 1");
+  if (opt.rule < 0 || opt.rule > 2) return fail(CCMF_EINVAL, "unknown penalty rule %d", opt.rule);
+  if (!(opt.rho0 >= 0.0) || !std::isfinite(opt.rho0)) return fail(CCMF_EINVAL, "rho0 must be >= 0 and finite");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(CCMF_EINVAL, "tol must be positive and finite");
+  if (nloads < 1 || !xi) return fail(CCMF_EINVAL, "need at least one load direction");
+  if (!geff || !iters) return fail(CCMF_EINVAL, "geff and iters outputs are required");
+  for (int64_t l = 0; l < nloads; ++l) {
+    const double nr = std::sqrt(xi[3 * l] * xi[3 * l] + xi[3 * l + 1] * xi[3 * l + 1] + xi[3 * l + 2] * xi[3 * l + 2]);
+    if (!(nr > 0.0) || !std::isfinite(nr)) return fail(CCMF_EINVAL, "load %lld is zero or not finite", (long long)l);
+  }
+  if (p->nfields * nloads > 65535) return fail(CCMF_EINVAL, "at most 65535 problems per solve");
+  int rc = ensure_state(p, nloads);
+  if (rc) return rc;
+  p->solved = false;
+
+  for (int64_t b = 0; b < p->B; ++b) {
+    const int64_t f = b / nloads, l = b % nloads;
+    Prob& P = p->probh[b];
+    std::memset(&P, 0, sizeof(P));
+    const double nr = std::sqrt(xi[3 * l] * xi[3 * l] + xi[3 * l + 1] * xi[3 * l + 1] + xi[3 * l + 2] * xi[3 * l + 2]);
+    for (int c = 0; c < 3; ++c) P.xibar[c] = xi[3 * l + c] / nr;
+    const bool any_pos = p->kmax[f] > 0.0;
+    P.rho0 = opt.rho0 > 0.0 ? opt.rho0 : (any_pos ? p->kmin[f] : 1.0);
+    P.lo = any_pos ? 0.1 * p->kmin[f] : 1.0;
+    P.hi = any_pos ? p->kmax[f] : 1.0;
+    P.rho = P.rho0;
+    P.rho_prev = P.rho0;
+    P.tol = tol;
+    P.delta = opt.delta;
+    P.rule = opt.rule;
+    P.max_iter = opt.max_iter;
+    P.all_zero = any_pos ? 0 : 1;
+    P.field = (int32_t)f;
+  }
+  HIP_TRY(hipMemcpyAsync(p->prob, p->probh, (size_t)p->B * sizeof(Prob), hipMemcpyHostToDevice, p->stream));
+  const Geo g = make_geo(p);
+  {
+    const int blocks = (int)std::min<uint64_t>(4096, (p->N + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_init<T>), dim3(blocks, (unsigned)p->B), dim3(kThreads), 0, p->stream, g,
+                       reinterpret_cast<const T*>(p->kap), reinterpret_cast<T*>(p->z[0]),
+                       reinterpret_cast<T*>(p->a[0]), p->prob);
+    HIP_LAUNCH_CHECK();
+  }
+  p->ev_used = 0;
+  bool all_done = false;
+  for (int it = 0; it < opt.max_iter && !all_done; ++it) {
+    if ((rc = run_iteration<T>(p, it, opt.time_kernels != 0))) return rc;
+    if ((it + 1) % opt.check_every == 0 || it + 1 == opt.max_iter) {
+      HIP_TRY(hipMemcpyAsync(p->probh, p->prob, (size_t)p->B * sizeof(Prob), hipMemcpyDeviceToHost, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+      all_done = true;
+      for (int64_t b = 0; b < p->B; ++b) all_done = all_done && p->probh[b].done != 0;
+      if (opt.time_kernels && (rc = harvest_events(p))) return rc;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(p->probh, p->prob, (size_t)p->B * sizeof(Prob), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (opt.time_kernels && (rc = harvest_events(p))) return rc;
+  int status = CCMF_OK;
+  for (int64_t b = 0; b < p->B; ++b) {
+    const Prob& P = p->probh[b];
+    if (P.done == 0) return fail(CCMF_EDEVICE, "problem %lld did not finish", (long long)b);
+    if (P.done == 2) status = CCMF_NOT_CONVERGED;
+    geff[b] = P.geff;
+    iters[b] = P.k + 1;
+    if (residual) residual[b] = P.res;
+    if (dual_est) dual_est[b] = P.dual;
+  }
+  p->solved = true;
+  if (phi_dev) {
+    HIP_TRY(hipMemcpyAsync(phi_dev, p->r, (size_t)p->B * p->N * sizeof(T), hipMemcpyDeviceToDevice, p->stream));
+  }
+  if (flux_dev) {
+    const int blocks = (int)std::min<uint64_t>(4096, (p->N + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_flux<T>), dim3(blocks, (unsigned)p->B), dim3(kThreads), 0, p->stream, g,
+                       reinterpret_cast<const T*>(p->z[0]), reinterpret_cast<const T*>(p->z[1]),
+                       reinterpret_cast<const T*>(p->a[0]), reinterpret_cast<const T*>(p->a[1]),
+                       reinterpret_cast<T*>(flux_dev), p->prob);
+    HIP_LAUNCH_CHECK();
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (status == CCMF_NOT_CONVERGED) fail(CCMF_NOT_CONVERGED, "max_iter reached before the tolerance");
+  return status;
+}
+
+template <typename T>
+int grad_impl(ccmf_plan_s* p, const double* dl, void* dkap) {
+  if (!p->solved) return fail(CCMF_ESTATE, "ccmf_grad_kappa needs a preceding ccmf_solve");
+  if (!dl || !dkap) return fail(CCMF_EINVAL, "null argument");
+  double* ddl = nullptr;
+  HIP_TRY(hipMalloc(&ddl, (size_t)p->B * sizeof(double)));
+  hipError_t e = hipMemcpyAsync(ddl, dl, (size_t)p->B * sizeof(double), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) {
+    const Geo g = make_geo(p);
+    const int blocks = (int)std::min<uint64_t>(4096, (p->N + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_grad<T>), dim3(blocks, (unsigned)p->nfields), dim3(kThreads), 0, p->stream, g,
+                       reinterpret_cast<const T*>(p->z[0]), reinterpret_cast<const T*>(p->z[1]),
+                       reinterpret_cast<const T*>(p->a[0]), reinterpret_cast<const T*>(p->a[1]),
+                       reinterpret_cast<const T*>(p->r), ddl, reinterpret_cast<T*>(dkap), p->prob);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  hipFree(ddl);
+  if (e != hipSuccess) return fail(CCMF_EDEVICE, "gradient: %s", hipGetErrorString(e));
+  return CCMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ccmf_setup(ccmf_plan* out, const int64_t dims[3], int64_t n_fields, int32_t dtype, const void* kappa_dev,
+               void* stream) {
+  if (!out || !dims || !kappa_dev) return fail(CCMF_EINVAL, "null argument");
+  *out = nullptr;
+  if (dtype != CCMF_F64 && dtype != CCMF_F32) return fail(CCMF_EINVAL, "unknown dtype %d", dtype);
+  if (n_fields < 1) return fail(CCMF_EINVAL, "n_fields must be >= 1");
+  int64_t N = 1;
+  for (int c = 0; c < 3; ++c) {
+    if (dims[c] < 1) return fail(CCMF_EINVAL, "dims[%d] = %lld must be >= 1", c, (long long)dims[c]);
+    N *= dims[c];
+    if (N >= (int64_t)1 << 31) return fail(CCMF_EINVAL, "grid too large (N must be < 2^31)");
+  }
+  ccmf_plan_s* p = new (std::nothrow) ccmf_plan_s();
+  if (!p) return fail(CCMF_ENOMEM, "host allocation failed");
+  p->dt = dtype;
+  p->esz = dtype == CCMF_F64 ? 8 : 4;
+  for (int c = 0; c < 3; ++c) p->n[c] = (int)dims[c];
+  p->N = (uint32_t)N;
+  p->nfields = n_fields;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  for (int c = 0; c < 3; ++c) {
+    if ((size_t)2 * 2 * p->n[c] * p->esz > 65536) {
+      delete p;
+      return fail(CCMF_EINVAL, "dims[%d] = %d exceeds the transform tile limit", c, p->n[c]);
+    }
+  }
+  int rc;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(CCMF_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  }
+  e = hipMalloc(&p->kap, (size_t)n_fields * N * p->esz);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(CCMF_ENOMEM, "kappa allocation: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpyAsync(p->kap, kappa_dev, (size_t)n_fields * N * p->esz, hipMemcpyDeviceToDevice, p->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(CCMF_EDEVICE, "kappa copy: %s", hipGetErrorString(e));
+  }
+  for (int c = 0; c < 3; ++c) {
+    rc = p->dt == CCMF_F64 ? upload_axis<double>(p->ax[c], p->n[c]) : upload_axis<float>(p->ax[c], p->n[c]);
+    if (rc) {
+      delete p;
+      return rc;
+    }
+  }
+  rc = p->dt == CCMF_F64 ? kappa_stats<double>(p) : kappa_stats<float>(p);
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return CCMF_OK;
+}
+
+int ccmf_solve(ccmf_plan p, const double* xi, int64_t n_loads, double tol, const ccmf_options* opt, double* geff,
+               int32_t* iters, double* residual, double* dual_est, void* phi_dev, void* flux_dev) {
+  if (!p) return fail(CCMF_EINVAL, "null plan");
+  return p->dt == CCMF_F64
+             ? solve_impl<double>(p, xi, n_loads, tol, opt, geff, iters, residual, dual_est, phi_dev, flux_dev)
+             : solve_impl<float>(p, xi, n_loads, tol, opt, geff, iters, residual, dual_est, phi_dev, flux_dev);
+}
+
+int ccmf_grad_kappa(ccmf_plan p, const double* dL_dgeff, void* dkappa_dev) {
+  if (!p) return fail(CCMF_EINVAL, "null plan");
+  return p->dt == CCMF_F64 ? grad_impl<double>(p, dL_dgeff, dkappa_dev) : grad_impl<float>(p, dL_dgeff, dkappa_dev);
+}
+
+int ccmf_kernel_times(ccmf_plan p, double* avg_ms, int64_t* count, double* bytes_per_launch) {
+  if (!p) return fail(CCMF_EINVAL, "null plan");
+  if (avg_ms) *avg_ms = p->kt_count ? p->kt_sum / (double)p->kt_count : 0.0;
+  if (count) *count = p->kt_count;
+  // fused update per voxel: read z (6), alpha, gamma, phi; write z (6), alpha
+  if (bytes_per_launch) *bytes_per_launch = 16.0 * (double)p->esz * (double)p->N;
+  p->kt_sum = 0.0;
+  p->kt_count = 0;
+  return CCMF_OK;
+}
+
+int ccmf_laplace_pinv(ccmf_plan p, const void* r_dev, void* phi_dev, int64_t count) {
+  if (!p || !r_dev || !phi_dev || count < 1) return fail(CCMF_EINVAL, "bad argument");
+  const size_t bytes = (size_t)count * p->N * p->esz;
+  if (r_dev != phi_dev) HIP_TRY(hipMemcpyAsync(phi_dev, r_dev, bytes, hipMemcpyDeviceToDevice, p->stream));
+  int rc = p->dt == CCMF_F64 ? launch_laplace<double>(p, reinterpret_cast<double*>(phi_dev), count, nullptr)
+                             : launch_laplace<float>(p, reinterpret_cast<float*>(phi_dev), count, nullptr);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return CCMF_OK;
+}
+
+int ccmf_hartley_axis(ccmf_plan p, void* data_dev, int64_t count, int32_t axis) {
+  if (!p || !data_dev || count < 1 || axis < 0 || axis > 2) return fail(CCMF_EINVAL, "bad argument");
+  if (p->n[axis] == 1) return CCMF_OK;
+  int rc = p->dt == CCMF_F64
+               ? launch_hartley<double>(p, reinterpret_cast<double*>(data_dev), count, axis, false, nullptr)
+               : launch_hartley<float>(p, reinterpret_cast<float*>(data_dev), count, axis, false, nullptr);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return CCMF_OK;
+}
+
+int ccmf_stream_copy(void* dst_dev, const void* src_dev, int64_t nbytes, void* stream) {
+  if (!dst_dev || !src_dev || nbytes < 0 || (nbytes % 16) != 0) return fail(CCMF_EINVAL, "bad argument");
+  const size_t n16 = (size_t)nbytes / 16;
+  if (n16 == 0) return CCMF_OK;
+  const unsigned blocks = (unsigned)std::min<size_t>(8192, (n16 + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kThreads), 0, reinterpret_cast<hipStream_t>(stream),
+                     reinterpret_cast<const uint4*>(src_dev), reinterpret_cast<uint4*>(dst_dev), n16);
+  HIP_LAUNCH_CHECK();
+  return CCMF_OK;
+}
+
+void ccmf_destroy(ccmf_plan p) { delete p; }
+
+const char* ccmf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
