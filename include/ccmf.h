@@ -86,7 +86,9 @@ int ccmf_setup(ccmf_plan* out, const int64_t dims[3], int64_t n_fields, int32_t 
  * geff:      host out, [B]: primal energy (1/N) sum gamma |xi^{k+1/2}| at the stopping iterate.
  * iters:     host out, [B]: number of xi-steps taken.  residual: host out, [B] (nullable).
  * dual_est:  host out, [B]: <A xibar, v^k> (nullable).
- * phi_dev:   device out, [B][N] node potential of the stopping iterate, zero mean (nullable).
+ * phi_dev:   device out, [B][N] double: node potential of the stopping iterate, zero mean
+ *            (nullable).  Always FP64: phi has magnitude O(N) while only its
+ *            differences enter the scheme, so it is computed and kept in FP64.
  * flux_dev:  device out, [B][3][N] face fluxes A* v^k, v_c[x] on face x + e_c/2 (nullable).
  * The solution state stays in the plan for ccmf_grad_kappa until the next solve. */
 int ccmf_solve(ccmf_plan p, const double* xi, int64_t n_loads, double tol, const ccmf_options* opt,
@@ -106,7 +108,8 @@ int ccmf_kernel_times(ccmf_plan p, double* avg_ms, int64_t* count, double* bytes
 
 /* Apply the spectral solve phi = (div^- grad^+)^dagger r (the pseudo-inverse in
  * eq:CCMF_FFT_Gamma_2) to `count` fields with the plan's transform kernels.
- * r_dev, phi_dev: device, [count][N] of the plan's dtype (may alias). */
+ * r_dev: device, [count][N] of the plan's dtype; phi_dev: device, [count][N] double
+ * (may alias r_dev in FP64 mode). */
 int ccmf_laplace_pinv(ccmf_plan p, const void* r_dev, void* phi_dev, int64_t count);
 
 /* One separable Hartley transform pass along `axis` (0, 1, 2) of `count` fields,

@@ -28,7 +28,7 @@ class SolveResult:
     residual: np.ndarray        # [F, L] |e^k - xi^{k+1/2}|_{L2} at the stopping iterate
     dual_est: np.ndarray        # [F, L] <A xibar, v^k>
     converged: bool
-    phi: Optional[torch.Tensor] = None    # [F, L, N1, N2, N3]
+    phi: Optional[torch.Tensor] = None    # [F, L, N1, N2, N3], float64
     flux: Optional[torch.Tensor] = None   # [F, L, 3, N1, N2, N3]
 
 
@@ -98,7 +98,7 @@ class Plan:
         dual = np.zeros(B)
         phi = flux = None
         if want_phi:
-            phi = torch.empty((self.n_fields, L) + self.dims, dtype=self.dtype, device=self.device)
+            phi = torch.empty((self.n_fields, L) + self.dims, dtype=torch.float64, device=self.device)
         if want_flux:
             flux = torch.empty((self.n_fields, L, 3) + self.dims, dtype=self.dtype, device=self.device)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -117,7 +117,7 @@ class Plan:
     def grad_kappa(self, dL_dgeff) -> torch.Tensor:
         """Envelope gradient of the last solve: sum_l dL/dgeff[f,l] * |xi*_{f,l}[x]|/N."""
         dl = np.ascontiguousarray(np.asarray(dL_dgeff, dtype=np.float64).reshape(-1))
-        if dl.size != self.n_fields * self.n_loads:
+        if self.n_loads and dl.size != self.n_fields * self.n_loads:
             raise ValueError("dL_dgeff must have one entry per (field, load) of the last solve")
         out = torch.empty((self.n_fields,) + self.dims, dtype=self.dtype, device=self.device)
         with torch.cuda.device(self.device):
@@ -134,9 +134,9 @@ class Plan:
         return avg.value, cnt.value, by.value
 
     def laplace_pinv(self, r: torch.Tensor) -> torch.Tensor:
-        """(div^- grad^+)^dagger applied to each field of r [..., N1, N2, N3]."""
+        """(div^- grad^+)^dagger applied to each field of r [..., N1, N2, N3]; float64 result."""
         r = r.to(self.dtype).contiguous()
-        out = torch.empty_like(r)
+        out = torch.empty(r.shape, dtype=torch.float64, device=r.device)
         count = r.numel() // self.N
         with torch.cuda.device(self.device):
             _lib.check(self._lib.ccmf_laplace_pinv(self._h, _dptr(r), _dptr(out), count))

@@ -46,9 +46,12 @@ int fail(int code, const char* fmt, ...) {
 struct Axis {
   int n = 1;
   std::vector<int> radix;
-  void* tw = nullptr;  // complex twiddles exp(-2 pi i t / n), t < n (plan dtype)
-  void* s = nullptr;   // 4 sin^2(pi q / n), q < n (plan dtype)
+  void* tw[2] = {nullptr, nullptr};  // complex twiddles exp(-2 pi i t / n), t < n: [0] double, [1] float
+  void* s[2] = {nullptr, nullptr};   // 4 sin^2(pi q / n), q < n: [0] double, [1] float
 };
+
+template <typename T>
+constexpr int prec_index() { return sizeof(T) == 8 ? 0 : 1; }
 
 std::vector<int> factor_radices(int n) {
   std::vector<int> r;
@@ -96,7 +99,8 @@ struct ccmf_plan_s {
   int64_t B = 0, nloads = 0;
   void* z[2] = {nullptr, nullptr};
   void* a[2] = {nullptr, nullptr};
-  void* r = nullptr;
+  void* r = nullptr;       // r = div^- A* w in the plan dtype (aliases phi in FP64 mode)
+  double* phi = nullptr;   // node potential, FP64 in both modes
   double* partials = nullptr;
   int nparts = 0;
   Prob* prob = nullptr;    // device
@@ -113,8 +117,10 @@ struct ccmf_plan_s {
   ~ccmf_plan_s() {
     hipFree(kap);
     for (int c = 0; c < 3; ++c) {
-      hipFree(ax[c].tw);
-      hipFree(ax[c].s);
+      for (int q = 0; q < 2; ++q) {
+        hipFree(ax[c].tw[q]);
+        hipFree(ax[c].s[q]);
+      }
     }
     free_state();
     for (auto e : ev) hipEventDestroy(e);
@@ -125,7 +131,10 @@ struct ccmf_plan_s {
       hipFree(a[p]);
       z[p] = a[p] = nullptr;
     }
-    hipFree(r);
+    if (r != (void*)phi) hipFree(r);
+    hipFree(phi);
+    r = nullptr;
+    phi = nullptr;
     hipFree(partials);
     hipFree(prob);
     if (probh) hipHostFree(probh);
@@ -152,23 +161,28 @@ Geo make_geo(const ccmf_plan_s* p) {
   return g;
 }
 
-template <typename T>
 int upload_axis(Axis& ax, int n) {
   ax.n = n;
   ax.radix = factor_radices(n);
-  std::vector<T> tw(2 * (size_t)n), s(n);
+  std::vector<double> tw(2 * (size_t)n), sv(n);
   for (int t = 0; t < n; ++t) {
-    // angles reduced exactly in integer arithmetic, evaluated in long double
-    const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)n;
-    tw[2 * t] = (T)cosl(ang);
-    tw[2 * t + 1] = (T)sinl(ang);
-    const long double sv = sinl(3.14159265358979323846264338327950288L * (long double)t / (long double)n);
-    s[t] = (T)(4.0L * sv * sv);
+    // angles from exact integer ratios, evaluated in long double, rounded once
+    const long double pi = 3.14159265358979323846264338327950288L;
+    const long double ang = -2.0L * pi * (long double)t / (long double)n;
+    tw[2 * t] = (double)cosl(ang);
+    tw[2 * t + 1] = (double)sinl(ang);
+    const long double sn = sinl(pi * (long double)t / (long double)n);
+    sv[t] = (double)(4.0L * sn * sn);
   }
-  HIP_TRY(hipMalloc(&ax.tw, tw.size() * sizeof(T)));
-  HIP_TRY(hipMalloc(&ax.s, s.size() * sizeof(T)));
-  HIP_TRY(hipMemcpy(ax.tw, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(ax.s, s.data(), s.size() * sizeof(T), hipMemcpyHostToDevice));
+  std::vector<float> tw32(tw.begin(), tw.end()), sv32(sv.begin(), sv.end());
+  HIP_TRY(hipMalloc(&ax.tw[0], tw.size() * sizeof(double)));
+  HIP_TRY(hipMalloc(&ax.s[0], sv.size() * sizeof(double)));
+  HIP_TRY(hipMalloc(&ax.tw[1], tw32.size() * sizeof(float)));
+  HIP_TRY(hipMalloc(&ax.s[1], sv32.size() * sizeof(float)));
+  HIP_TRY(hipMemcpy(ax.tw[0], tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ax.s[0], sv.data(), sv.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ax.tw[1], tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ax.s[1], sv32.data(), sv32.size() * sizeof(float), hipMemcpyHostToDevice));
   return CCMF_OK;
 }
 
@@ -180,9 +194,47 @@ int lines_per_tile(int n, size_t esz, int lines_total) {
   return nl;
 }
 
-// Launch one Hartley pass along `axis` over `count` fields of `data`.
-template <typename T>
-int launch_hartley(ccmf_plan_s* p, T* data, int64_t count, int axis, bool middle, const Prob* prob) {
+bool is_pow2_len(int n) { return n >= 2 && n <= 2048 && (n & (n - 1)) == 0; }
+
+// Launch the power-of-two Hartley kernel: NLC complex lines (2 NLC real lines) per
+// block, NLC * TPL <= 512 threads, padded LDS tile within 64 KiB.
+template <typename TI, typename TO, typename TC, int N>
+int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
+              bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob) {
+  constexpr int E = pow2::Plan<N>::E, TPL = N / E;
+  int nlc = 16;
+  while (nlc > 1 && (nlc * TPL > 512 || (size_t)nlc * (N + 1) * 2 * sizeof(TC) > 65536)) nlc >>= 1;
+  while (nlc > 1 && 2 * (nlc >> 1) >= A.lines_total) nlc >>= 1;  // do not pad tiny line counts
+  const int nl = 2 * nlc;
+  int lognl = 0;
+  while ((1 << lognl) < nl) ++lognl;
+  A.nl = nl;
+  A.lognl = lognl;
+  A.tiles_per_outer = (A.lines_total + nl - 1) / nl;
+  const size_t lds = (size_t)nlc * (N + 1) * 2 * sizeof(TC);
+  if (lds > 65536 || nlc * TPL > 512) return fail(CCMF_EINVAL, "transform length %d too large for the LDS tile", N);
+  dim3 grid((unsigned)(outers * A.tiles_per_outer), (unsigned)count);
+  dim3 block((unsigned)(nlc * TPL));
+  const pow2::CX<TC>* tw = reinterpret_cast<const pow2::CX<TC>*>(twp);
+  if (middle) {
+    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, false, true>), grid, block, lds, p->stream, in, out, tw, A, s1,
+                       s2, s3, prob);
+  } else if (contig) {
+    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, true, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
+                       s2, s3, prob);
+  } else {
+    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, false, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
+                       s2, s3, prob);
+  }
+  HIP_LAUNCH_CHECK();
+  return CCMF_OK;
+}
+
+// Launch one Hartley pass along `axis` over `count` fields: load TI from `in`,
+// compute in TC, store TO to `out` (same layout, may alias).
+template <typename TI, typename TO, typename TC>
+int launch_hartley(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, int axis, bool middle,
+                   const Prob* prob) {
   const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
   const Axis& ax = p->ax[axis];
   DhtArgs A;
@@ -219,38 +271,57 @@ int launch_hartley(ccmf_plan_s* p, T* data, int64_t count, int axis, bool middle
     A.os = n3;
     outers = n2;
   }
-  A.nl = lines_per_tile(A.n, sizeof(T), A.lines_total);
+  constexpr int q = prec_index<TC>();
+  const TC* s1 = reinterpret_cast<const TC*>(p->ax[0].s[q]);
+  const TC* s2 = reinterpret_cast<const TC*>(p->ax[1].s[q]);
+  const TC* s3 = reinterpret_cast<const TC*>(p->ax[2].s[q]);
+  if (is_pow2_len(A.n)) {
+    switch (A.n) {
+      case 2: return launch_p2<TI, TO, TC, 2>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 4: return launch_p2<TI, TO, TC, 4>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 8: return launch_p2<TI, TO, TC, 8>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 16: return launch_p2<TI, TO, TC, 16>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 32: return launch_p2<TI, TO, TC, 32>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 64: return launch_p2<TI, TO, TC, 64>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 128: return launch_p2<TI, TO, TC, 128>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 256: return launch_p2<TI, TO, TC, 256>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 512: return launch_p2<TI, TO, TC, 512>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 1024: return launch_p2<TI, TO, TC, 1024>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 2048: return launch_p2<TI, TO, TC, 2048>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      default: break;
+    }
+  }
+  A.nl = lines_per_tile(A.n, sizeof(TC), A.lines_total);
   A.tiles_per_outer = (A.lines_total + A.nl - 1) / A.nl;
-  const size_t lds = (size_t)2 * A.nl * A.n * sizeof(T);
+  const size_t lds = (size_t)2 * A.nl * A.n * sizeof(TC);
   if (lds > 65536) return fail(CCMF_EINVAL, "transform length %d too large for the LDS tile", A.n);
   dim3 grid((unsigned)(outers * A.tiles_per_outer), (unsigned)count);
-  const C2<T>* tw = reinterpret_cast<const C2<T>*>(ax.tw);
-  const T* s1 = reinterpret_cast<const T*>(p->ax[0].s);
-  const T* s2 = reinterpret_cast<const T*>(p->ax[1].s);
-  const T* s3 = reinterpret_cast<const T*>(p->ax[2].s);
+  const C2<TC>* tw = reinterpret_cast<const C2<TC>*>(ax.tw[q]);
   if (middle) {
-    hipLaunchKernelGGL((k_hartley<T, false, true>), grid, dim3(kThreads), lds, p->stream, data, tw, A,
-                       s1, s2, s3, prob);
+    hipLaunchKernelGGL((k_hartley<TI, TO, TC, false, true>), grid, dim3(kThreads), lds, p->stream, in, out, tw,
+                       A, s1, s2, s3, prob);
   } else if (contig) {
-    hipLaunchKernelGGL((k_hartley<T, true, false>), grid, dim3(kThreads), lds, p->stream, data, tw, A,
-                       s1, s2, s3, prob);
+    hipLaunchKernelGGL((k_hartley<TI, TO, TC, true, false>), grid, dim3(kThreads), lds, p->stream, in, out, tw,
+                       A, s1, s2, s3, prob);
   } else {
-    hipLaunchKernelGGL((k_hartley<T, false, false>), grid, dim3(kThreads), lds, p->stream, data, tw, A,
-                       s1, s2, s3, prob);
+    hipLaunchKernelGGL((k_hartley<TI, TO, TC, false, false>), grid, dim3(kThreads), lds, p->stream, in, out, tw,
+                       A, s1, s2, s3, prob);
   }
   HIP_LAUNCH_CHECK();
   return CCMF_OK;
 }
 
-// phi = (div^- grad^+)^dagger r in place: k, j, [i, scale, i], j, k
+// phi = (div^- grad^+)^dagger r: forward passes along k and j in place on r (the
+// plan dtype), the fused axis-i pass reads r and writes phi in FP64, the inverse
+// passes along j and k run in FP64 in place on phi.
 template <typename T>
-int launch_laplace(ccmf_plan_s* p, T* data, int64_t count, const Prob* prob) {
+int launch_laplace(ccmf_plan_s* p, T* r, double* phi, int64_t count, const Prob* prob) {
   int rc;
-  if (p->n[2] > 1 && (rc = launch_hartley<T>(p, data, count, 2, false, prob))) return rc;
-  if (p->n[1] > 1 && (rc = launch_hartley<T>(p, data, count, 1, false, prob))) return rc;
-  if ((rc = launch_hartley<T>(p, data, count, 0, true, prob))) return rc;
-  if (p->n[1] > 1 && (rc = launch_hartley<T>(p, data, count, 1, false, prob))) return rc;
-  if (p->n[2] > 1 && (rc = launch_hartley<T>(p, data, count, 2, false, prob))) return rc;
+  if (p->n[2] > 1 && (rc = launch_hartley<T, T, T>(p, r, r, count, 2, false, prob))) return rc;
+  if (p->n[1] > 1 && (rc = launch_hartley<T, T, T>(p, r, r, count, 1, false, prob))) return rc;
+  if ((rc = launch_hartley<T, double, double>(p, r, phi, count, 0, true, prob))) return rc;
+  if (p->n[1] > 1 && (rc = launch_hartley<double, double, double>(p, phi, phi, count, 1, false, prob))) return rc;
+  if (p->n[2] > 1 && (rc = launch_hartley<double, double, double>(p, phi, phi, count, 2, false, prob))) return rc;
   return CCMF_OK;
 }
 
@@ -301,7 +372,12 @@ int ensure_state(ccmf_plan_s* p, int64_t nloads) {
     HIP_TRY(hipMalloc(&p->z[q], (size_t)B * 6 * N * p->esz));
     HIP_TRY(hipMalloc(&p->a[q], (size_t)B * N * p->esz));
   }
-  HIP_TRY(hipMalloc(&p->r, (size_t)B * N * p->esz));
+  HIP_TRY(hipMalloc(&p->phi, (size_t)B * N * sizeof(double)));
+  if (p->dt == CCMF_F64) {
+    p->r = p->phi;
+  } else {
+    HIP_TRY(hipMalloc(&p->r, (size_t)B * N * p->esz));
+  }
   HIP_TRY(hipMalloc(&p->partials, (size_t)B * p->upd_blocks * kNQ * sizeof(double)));
   HIP_TRY(hipMalloc(&p->prob, (size_t)B * sizeof(Prob)));
   HIP_TRY(hipHostMalloc((void**)&p->probh, (size_t)B * sizeof(Prob), hipHostMallocDefault));
@@ -346,11 +422,11 @@ int run_iteration(ccmf_plan_s* p, int it, bool timed) {
   dim3 grid((unsigned)p->upd_blocks, (unsigned)p->B);
   hipLaunchKernelGGL((k_div<T>), grid, dim3(kThreads), 0, p->stream, g, z0, a0, r, p->prob);
   HIP_LAUNCH_CHECK();
-  int rc = launch_laplace<T>(p, r, p->B, p->prob);
+  int rc = launch_laplace<T>(p, r, p->phi, p->B, p->prob);
   if (rc) return rc;
   hipEvent_t e0, e1;
   if (timed && (rc = record_event(p, &e0))) return rc;
-  hipLaunchKernelGGL((k_update<T>), grid, dim3(kThreads), 0, p->stream, g, kap, z0, a0, r, z1, a1,
+  hipLaunchKernelGGL((k_update<T>), grid, dim3(kThreads), 0, p->stream, g, kap, z0, a0, p->phi, z1, a1,
                      p->partials, p->prob);
   HIP_LAUNCH_CHECK();
   if (timed && (rc = record_event(p, &e1))) return rc;
@@ -442,7 +518,8 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
   }
   p->solved = true;
   if (phi_dev) {
-    HIP_TRY(hipMemcpyAsync(phi_dev, p->r, (size_t)p->B * p->N * sizeof(T), hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(phi_dev, p->phi, (size_t)p->B * p->N * sizeof(double), hipMemcpyDeviceToDevice,
+                           p->stream));
   }
   if (flux_dev) {
     const int blocks = (int)std::min<uint64_t>(4096, (p->N + kThreads - 1) / kThreads);
@@ -470,7 +547,7 @@ int grad_impl(ccmf_plan_s* p, const double* dl, void* dkap) {
     hipLaunchKernelGGL((k_grad<T>), dim3(blocks, (unsigned)p->nfields), dim3(kThreads), 0, p->stream, g,
                        reinterpret_cast<const T*>(p->z[0]), reinterpret_cast<const T*>(p->z[1]),
                        reinterpret_cast<const T*>(p->a[0]), reinterpret_cast<const T*>(p->a[1]),
-                       reinterpret_cast<const T*>(p->r), ddl, reinterpret_cast<T*>(dkap), p->prob);
+                       p->phi, ddl, reinterpret_cast<T*>(dkap), p->prob);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -526,7 +603,7 @@ int ccmf_setup(ccmf_plan* out, const int64_t dims[3], int64_t n_fields, int32_t 
     return fail(CCMF_EDEVICE, "kappa copy: %s", hipGetErrorString(e));
   }
   for (int c = 0; c < 3; ++c) {
-    rc = p->dt == CCMF_F64 ? upload_axis<double>(p->ax[c], p->n[c]) : upload_axis<float>(p->ax[c], p->n[c]);
+    rc = upload_axis(p->ax[c], p->n[c]);
     if (rc) {
       delete p;
       return rc;
@@ -558,8 +635,9 @@ int ccmf_kernel_times(ccmf_plan p, double* avg_ms, int64_t* count, double* bytes
   if (!p) return fail(CCMF_EINVAL, "null plan");
   if (avg_ms) *avg_ms = p->kt_count ? p->kt_sum / (double)p->kt_count : 0.0;
   if (count) *count = p->kt_count;
-  // fused update per voxel: read z (6), alpha, gamma, phi; write z (6), alpha
-  if (bytes_per_launch) *bytes_per_launch = 16.0 * (double)p->esz * (double)p->N;
+  // fused update per voxel: read z (6), alpha, gamma (plan dtype) and phi (FP64);
+  // write z (6), alpha (plan dtype)
+  if (bytes_per_launch) *bytes_per_launch = (15.0 * (double)p->esz + 8.0) * (double)p->N;
   p->kt_sum = 0.0;
   p->kt_count = 0;
   return CCMF_OK;
@@ -567,21 +645,38 @@ int ccmf_kernel_times(ccmf_plan p, double* avg_ms, int64_t* count, double* bytes
 
 int ccmf_laplace_pinv(ccmf_plan p, const void* r_dev, void* phi_dev, int64_t count) {
   if (!p || !r_dev || !phi_dev || count < 1) return fail(CCMF_EINVAL, "bad argument");
-  const size_t bytes = (size_t)count * p->N * p->esz;
-  if (r_dev != phi_dev) HIP_TRY(hipMemcpyAsync(phi_dev, r_dev, bytes, hipMemcpyDeviceToDevice, p->stream));
-  int rc = p->dt == CCMF_F64 ? launch_laplace<double>(p, reinterpret_cast<double*>(phi_dev), count, nullptr)
-                             : launch_laplace<float>(p, reinterpret_cast<float*>(phi_dev), count, nullptr);
+  const size_t n = (size_t)count * p->N;
+  void* tmp = nullptr;
+  if (p->dt == CCMF_F64) {
+    if (r_dev != phi_dev) HIP_TRY(hipMemcpyAsync(phi_dev, r_dev, n * 8, hipMemcpyDeviceToDevice, p->stream));
+    tmp = phi_dev;
+  } else {
+    HIP_TRY(hipMalloc(&tmp, n * 4));
+    HIP_TRY(hipMemcpyAsync(tmp, r_dev, n * 4, hipMemcpyDeviceToDevice, p->stream));
+  }
+  int rc = p->dt == CCMF_F64
+               ? launch_laplace<double>(p, reinterpret_cast<double*>(tmp), reinterpret_cast<double*>(phi_dev),
+                                        count, nullptr)
+               : launch_laplace<float>(p, reinterpret_cast<float*>(tmp), reinterpret_cast<double*>(phi_dev),
+                                       count, nullptr);
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (tmp != phi_dev) hipFree(tmp);
   if (rc) return rc;
-  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (e != hipSuccess) return fail(CCMF_EDEVICE, "laplace: %s", hipGetErrorString(e));
   return CCMF_OK;
 }
 
 int ccmf_hartley_axis(ccmf_plan p, void* data_dev, int64_t count, int32_t axis) {
   if (!p || !data_dev || count < 1 || axis < 0 || axis > 2) return fail(CCMF_EINVAL, "bad argument");
   if (p->n[axis] == 1) return CCMF_OK;
-  int rc = p->dt == CCMF_F64
-               ? launch_hartley<double>(p, reinterpret_cast<double*>(data_dev), count, axis, false, nullptr)
-               : launch_hartley<float>(p, reinterpret_cast<float*>(data_dev), count, axis, false, nullptr);
+  int rc;
+  if (p->dt == CCMF_F64) {
+    double* d = reinterpret_cast<double*>(data_dev);
+    rc = launch_hartley<double, double, double>(p, d, d, count, axis, false, nullptr);
+  } else {
+    float* d = reinterpret_cast<float*>(data_dev);
+    rc = launch_hartley<float, float, float>(p, d, d, count, axis, false, nullptr);
+  }
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(p->stream));
   return CCMF_OK;

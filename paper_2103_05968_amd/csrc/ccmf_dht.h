@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ccmf_fft_pow2.h"
 #include "ccmf_kernels.h"
 
 namespace ccmf {
@@ -60,6 +61,7 @@ struct DhtArgs {
   // spectral scaling of the fused middle pass
   double scale;         // 1/N
   int32_t n2, n3;       // sizes of the other two axes (middle pass: line index = q3, outer = q2)
+  int32_t lognl;        // log2(nl) for the power-of-two kernel
 };
 
 // forward DFT of radix R on registers, exp(-2 pi i p r / R)
@@ -200,60 +202,200 @@ __device__ __forceinline__ T hartley_of(const C2<T>* F, int n, int t, int s) {
 }
 
 // One Hartley pass over a tile; MIDDLE additionally applies m(q) and the second
-// transform along the same axis (the axis-1 pass of the solve).
-template <typename T, bool CONTIG, bool MIDDLE>
+// transform along the same axis (the axis-1 pass of the solve).  Samples are
+// loaded as TI, transformed in TC (LDS and twiddles) and stored as TO, so the
+// half of the solve after the division by lambda can run in FP64 for FP32
+// fields: the potential has magnitude O(N) while the update needs its O(1)
+// differences.  `in` and `out` have the same layout and may alias.
+template <typename TI, typename TO, typename TC, bool CONTIG, bool MIDDLE>
 __global__ void __launch_bounds__(kThreads)
-k_hartley(T* __restrict__ data, const C2<T>* __restrict__ tw, DhtArgs A,
-          const T* __restrict__ s1, const T* __restrict__ s2, const T* __restrict__ s3,
+k_hartley(const TI* in, TO* out, const C2<TC>* __restrict__ tw, DhtArgs A,
+          const TC* __restrict__ s1, const TC* __restrict__ s2, const TC* __restrict__ s3,
           const Prob* __restrict__ prob) {
   extern __shared__ unsigned char smem_raw[];
   const int b = blockIdx.y;
   if (prob != nullptr && prob[b].done) return;
   const int n = A.n, nl = A.nl, nlc = nl >> 1;
-  C2<T>* bufA = reinterpret_cast<C2<T>*>(smem_raw);
-  C2<T>* bufB = bufA + nlc * n;
-  T* bufAr = reinterpret_cast<T*>(bufA);
+  C2<TC>* bufA = reinterpret_cast<C2<TC>*>(smem_raw);
+  C2<TC>* bufB = bufA + nlc * n;
+  TC* bufAr = reinterpret_cast<TC*>(bufA);
 
   const int outer = blockIdx.x / A.tiles_per_outer;
   const int lt = blockIdx.x - outer * A.tiles_per_outer;
   const int line0 = lt * nl;
   const int nvalid = min(nl, A.lines_total - line0);
-  T* base = data + (size_t)b * A.field_stride + (size_t)outer * A.os + (size_t)line0 * A.ls;
+  const size_t off = (size_t)b * A.field_stride + (size_t)outer * A.os + (size_t)line0 * A.ls;
+  const TI* src = in + off;
+  TO* dst = out + off;
 
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     int s, t;
     tile_coords<CONTIG>(e, n, nl, s, t);
-    const T v = (t < nvalid) ? base[(size_t)s * A.ss + (size_t)t * A.ls] : T(0);
+    const TC v = (t < nvalid) ? TC(src[(size_t)s * A.ss + (size_t)t * A.ls]) : TC(0);
     bufAr[((t >> 1) * n + s) * 2 + (t & 1)] = v;
   }
   __syncthreads();
-  C2<T>* F = fft_lines<T>(bufA, bufB, tw, A, nlc);
+  C2<TC>* F = fft_lines<TC>(bufA, bufB, tw, A, nlc);
 
   if (MIDDLE) {
-    // H along axis 0 is known; scale by m(q1, q2, q3) and transform again
-    C2<T>* G = (F == bufA) ? bufB : bufA;
-    T* Gr = reinterpret_cast<T*>(G);
+    // H along axis 0 is known; scale by m(q1, q2, q3) = 1/(lambda N) and transform again
+    C2<TC>* G = (F == bufA) ? bufB : bufA;
+    TC* Gr = reinterpret_cast<TC*>(G);
     for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
       int s, t;
       tile_coords<CONTIG>(e, n, nl, s, t);
       const int q2 = outer, q3 = line0 + t;
-      T h = hartley_of<T>(F, n, t, s);
-      T m = T(0);
+      const TC h = hartley_of<TC>(F, n, t, s);
+      TC m = TC(0);
       if (t < nvalid) {
-        const T lam = s1[s] + s2[q2] + s3[q3];
-        m = (lam > T(0)) ? T(A.scale) / lam : T(0);  // lambda = -lam; sign applied below
+        const TC lam = s1[s] + s2[q2] + s3[q3];   // lambda(q) = -lam
+        m = (lam > TC(0)) ? -TC(A.scale) / lam : TC(0);
       }
-      Gr[((t >> 1) * n + s) * 2 + (t & 1)] = -h * m;
+      Gr[((t >> 1) * n + s) * 2 + (t & 1)] = h * m;
     }
     __syncthreads();
-    // fft_lines ping-pongs between its two arguments starting from the first
-    F = fft_lines<T>(G, (G == bufA) ? bufB : bufA, tw, A, nlc);
+    F = fft_lines<TC>(G, (G == bufA) ? bufB : bufA, tw, A, nlc);
   }
 
   for (int e = threadIdx.x; e < nl * n; e += blockDim.x) {
     int s, t;
     tile_coords<CONTIG>(e, n, nl, s, t);
-    if (t < nvalid) base[(size_t)s * A.ss + (size_t)t * A.ls] = hartley_of<T>(F, n, t, s);
+    if (t < nvalid) dst[(size_t)s * A.ss + (size_t)t * A.ls] = TO(hartley_of<TC>(F, n, t, s));
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Power-of-two line lengths: compile-time plan (ccmf_fft_pow2.h).  The block
+// holds NLC = blockDim / TPL complex lines (2 NLC real lines), each padded by one
+// element so that the line-strided LDS accesses of the column passes spread
+// over the banks.  Stages run in place: read E values, compute, barrier, write.
+// ---------------------------------------------------------------------------
+template <typename TC, int N>
+__device__ __forceinline__ void fft_line_p2(pow2::CX<TC>* line, int t, const pow2::CX<TC>* __restrict__ tw) {
+  using P = pow2::Plan<N>;
+  constexpr int E = P::E, TPL = N / E;
+  pow2::CX<TC> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = line[t + TPL * e];
+  pow2::stage_compute<TC, N, E, P::R0, 1>(v, t, tw);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E / P::R0; ++m)
+#pragma unroll
+    for (int r = 0; r < P::R0; ++r) line[pow2::stage_out_pos<N, E, P::R0, 1>(t, m, r)] = v[m + r * (E / P::R0)];
+  __syncthreads();
+  if constexpr (P::R1 > 0) {
+    constexpr int NS = P::R0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = line[t + TPL * e];
+    pow2::stage_compute<TC, N, E, P::R1, NS>(v, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E / P::R1; ++m)
+#pragma unroll
+      for (int r = 0; r < P::R1; ++r)
+        line[pow2::stage_out_pos<N, E, P::R1, NS>(t, m, r)] = v[m + r * (E / P::R1)];
+    __syncthreads();
+  }
+  if constexpr (P::R2 > 0) {
+    constexpr int NS = P::R0 * P::R1;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = line[t + TPL * e];
+    pow2::stage_compute<TC, N, E, P::R2, NS>(v, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E / P::R2; ++m)
+#pragma unroll
+      for (int r = 0; r < P::R2; ++r)
+        line[pow2::stage_out_pos<N, E, P::R2, NS>(t, m, r)] = v[m + r * (E / P::R2)];
+    __syncthreads();
+  }
+}
+
+template <typename TC, int N>
+__device__ __forceinline__ TC hartley_p2(const pow2::CX<TC>* L, int lp, int line, int s) {
+  const pow2::CX<TC> zq = L[(line >> 1) * lp + s];
+  const pow2::CX<TC> zm = L[(line >> 1) * lp + ((N - s) & (N - 1))];
+  if ((line & 1) == 0) return TC(0.5) * ((zq.x + zm.x) - (zq.y - zm.y));
+  return TC(0.5) * ((zq.y + zm.y) + (zq.x - zm.x));
+}
+
+template <bool CONTIG, int N>
+__device__ __forceinline__ void tile_coords_p2(int e, int lognl, int& s, int& line) {
+  if (CONTIG) {
+    line = e / N;
+    s = e & (N - 1);
+  } else {
+    s = e >> lognl;
+    line = e & ((1 << lognl) - 1);
+  }
+}
+
+template <typename TI, typename TO, typename TC, int N, bool CONTIG, bool MIDDLE>
+__global__ void __launch_bounds__(512)
+k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs A,
+             const TC* __restrict__ s1, const TC* __restrict__ s2, const TC* __restrict__ s3,
+             const Prob* __restrict__ prob) {
+  extern __shared__ unsigned char smem_raw[];
+  const int b = blockIdx.y;
+  if (prob != nullptr && prob[b].done) return;
+  using P = pow2::Plan<N>;
+  constexpr int E = P::E, TPL = N / E, LP = N + 1;
+  const int nl = 1 << A.lognl;
+  pow2::CX<TC>* L = reinterpret_cast<pow2::CX<TC>*>(smem_raw);
+  TC* Lr = reinterpret_cast<TC*>(smem_raw);
+  const int c = threadIdx.x / TPL, t = threadIdx.x & (TPL - 1);
+
+  const int outer = blockIdx.x / A.tiles_per_outer;
+  const int lt = blockIdx.x - outer * A.tiles_per_outer;
+  const int line0 = lt * nl;
+  const int nvalid = min(nl, A.lines_total - line0);
+  const size_t off = (size_t)b * A.field_stride + (size_t)outer * A.os + (size_t)line0 * A.ls;
+  const TI* src = in + off;
+  TO* dst = out + off;
+  const int total = nl * N;
+
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int s, l;
+    tile_coords_p2<CONTIG, N>(e, A.lognl, s, l);
+    const TC v = (l < nvalid) ? TC(src[(size_t)s * A.ss + (size_t)l * A.ls]) : TC(0);
+    Lr[((l >> 1) * LP + s) * 2 + (l & 1)] = v;
+  }
+  __syncthreads();
+  fft_line_p2<TC, N>(L + c * LP, t, tw);
+
+  if constexpr (MIDDLE) {
+    // Scale the Hartley coefficients by m(q) = 1/(lambda(q) N) and repack them
+    // as the next transform's input.  Positions s and N-s of a complex line hold
+    // both coefficients of its two real lines at s and N-s, and lambda(s) =
+    // lambda(N-s), so each thread rewrites its own pairs in place.
+    const int la = 2 * c, lb = 2 * c + 1;
+    const TC sa = (la < nvalid) ? s2[outer] + s3[line0 + la] : TC(-1);
+    const TC sb = (lb < nvalid) ? s2[outer] + s3[line0 + lb] : TC(-1);
+    pow2::CX<TC>* Lc = L + c * LP;
+    for (int sp = t; sp <= N / 2; sp += TPL) {
+      const int sm = (N - sp) & (N - 1);
+      const pow2::CX<TC> zs = Lc[sp], zm = Lc[sm];
+      const TC ha_s = TC(0.5) * ((zs.x + zm.x) - (zs.y - zm.y));
+      const TC hb_s = TC(0.5) * ((zs.y + zm.y) + (zs.x - zm.x));
+      const TC ha_m = TC(0.5) * ((zm.x + zs.x) - (zm.y - zs.y));
+      const TC hb_m = TC(0.5) * ((zm.y + zs.y) + (zm.x - zs.x));
+      const TC s1v = s1[sp];
+      const TC lam_a = s1v + sa, lam_b = s1v + sb;     // lambda(q) = -lam
+      const TC ma = (sa >= TC(0) && lam_a > TC(0)) ? -TC(A.scale) / lam_a : TC(0);
+      const TC mb = (sb >= TC(0) && lam_b > TC(0)) ? -TC(A.scale) / lam_b : TC(0);
+      Lc[sp] = {ha_s * ma, hb_s * mb};
+      Lc[sm] = {ha_m * ma, hb_m * mb};
+    }
+    __syncthreads();
+    fft_line_p2<TC, N>(L + c * LP, t, tw);
+  }
+
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int s, l;
+    tile_coords_p2<CONTIG, N>(e, A.lognl, s, l);
+    if (l < nvalid) dst[(size_t)s * A.ss + (size_t)l * A.ls] = TO(hartley_p2<TC, N>(L, LP, l, s));
   }
 }
 

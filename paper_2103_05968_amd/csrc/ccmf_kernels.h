@@ -181,7 +181,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __restrict__ a,
-         const T* __restrict__ phi, T* __restrict__ zn, T* __restrict__ an,
+         const double* __restrict__ phi, T* __restrict__ zn, T* __restrict__ an,
          double* __restrict__ partials, const Prob* __restrict__ prob) {
   const int b = blockIdx.y;
   const Prob& P = prob[b];
@@ -190,11 +190,10 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
   const T ir = T(1.0 / P.rho), irp = T(1.0 / P.rho_prev);
   const T c_relax = T(2.0 * (1.0 - P.delta)), c_old = T(1.0 - 2.0 * P.delta);
   const T s = T(0.70710678118654752440);
-  const T xb[3] = {T(P.xibar[0]), T(P.xibar[1]), T(P.xibar[2])};
   const T* gam = kap + (size_t)P.field * g.N;
   const T* zb = z + (size_t)b * 6 * g.N;
   const T* ab = a + (size_t)b * g.N;
-  const T* pb = phi + (size_t)b * g.N;
+  const double* pb = phi + (size_t)b * g.N;
   T* znb = zn + (size_t)b * 6 * g.N;
   T* anb = an + (size_t)b * g.N;
 
@@ -211,7 +210,7 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
     const Nbr nb = neighbours(g, x);
     const T al = ab[x];
     const T bx = beta_of(al, irp, ir);
-    const T ph = pb[x];
+    const double ph = pb[x];
     const T gm = gam[x];
     T zo[6], xh[6];
 #pragma unroll
@@ -220,8 +219,9 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
     for (int c = 0; c < 3; ++c) {
       const T w2p = beta_of(ab[nb.p[c]], irp, ir) * zb[(size_t)(c + 3) * g.N + nb.p[c]];
       const T w1m = beta_of(ab[nb.m[c]], irp, ir) * zb[(size_t)c * g.N + nb.m[c]];
-      const T tp = xb[c] + (pb[nb.p[c]] - ph);
-      const T tm = xb[c] + (ph - pb[nb.m[c]]);
+      // xibar + grad^+ phi formed in FP64: phi is O(N), its differences O(1)
+      const T tp = T(P.xibar[c] + (pb[nb.p[c]] - ph));
+      const T tm = T(P.xibar[c] + (ph - pb[nb.m[c]]));
       xh[c] = tp * s + T(0.5) * (bx * zo[c] - w2p);
       xh[c + 3] = tm * s + T(0.5) * (bx * zo[c + 3] - w1m);
     }
@@ -384,7 +384,7 @@ k_flux(Geo g, const T* __restrict__ z0, const T* __restrict__ z1, const T* __res
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_grad(Geo g, const T* __restrict__ z0, const T* __restrict__ z1, const T* __restrict__ a0,
-       const T* __restrict__ a1, const T* __restrict__ phi, const double* __restrict__ dl,
+       const T* __restrict__ a1, const double* __restrict__ phi, const double* __restrict__ dl,
        T* __restrict__ dkap, const Prob* __restrict__ prob) {
   // d geff / d gamma[x] = |xi^{k+1/2}[x]| / N, xi^{k+1/2} rebuilt from the stopping state
   const int f = blockIdx.y;
@@ -399,18 +399,17 @@ k_grad(Geo g, const T* __restrict__ z0, const T* __restrict__ z1, const T* __res
       const int par = P.k & 1;
       const T* zb = (par ? z1 : z0) + (size_t)b * 6 * g.N;
       const T* ab = (par ? a1 : a0) + (size_t)b * g.N;
-      const T* pb = phi + (size_t)b * g.N;
+      const double* pb = phi + (size_t)b * g.N;
       const T ir = T(1.0 / P.rho), irp = T(1.0 / P.rho_prev);
       const T bx = beta_of(ab[x], irp, ir);
-      const T ph = pb[x];
+      const double ph = pb[x];
       T xn2 = T(0);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T xbc = T(P.xibar[c]);
         const T w2p = beta_of(ab[nb.p[c]], irp, ir) * zb[(size_t)(c + 3) * g.N + nb.p[c]];
         const T w1m = beta_of(ab[nb.m[c]], irp, ir) * zb[(size_t)c * g.N + nb.m[c]];
-        const T x1 = (xbc + (pb[nb.p[c]] - ph)) * s + T(0.5) * (bx * zb[(size_t)c * g.N + x] - w2p);
-        const T x2 = (xbc + (ph - pb[nb.m[c]])) * s + T(0.5) * (bx * zb[(size_t)(c + 3) * g.N + x] - w1m);
+        const T x1 = T(P.xibar[c] + (pb[nb.p[c]] - ph)) * s + T(0.5) * (bx * zb[(size_t)c * g.N + x] - w2p);
+        const T x2 = T(P.xibar[c] + (ph - pb[nb.m[c]])) * s + T(0.5) * (bx * zb[(size_t)(c + 3) * g.N + x] - w1m);
         xn2 += x1 * x1 + x2 * x2;
       }
       out += T(dl[b]) * sqrt(xn2) * invN;
