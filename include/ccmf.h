@@ -68,6 +68,11 @@ typedef struct {
                           iterations (the kernels stop by themselves); 0 selects 32          */
   int32_t time_kernels;/* nonzero: time every launch of the fused update kernel with HIP
                           events on the plan's stream (read with ccmf_kernel_times)         */
+  double bb_min_corr;  /* Barzilai-Borwein estimate used only if <dv,de>/(|dv||de|) >= this,
+                          else the Lorenz-Tran-Dinh value; 0 selects 0.2                    */
+  double eta0;         /* safeguard: |log(rho_{k+1}/rho_k)| <= log(1 + eta0/(1+k/k0)^2), a
+                          summable variation; 0 selects 1.0                                  */
+  double k0;           /* see eta0; 0 selects 100                                             */
 } ccmf_options;
 
 /* Create a plan for n_fields crack-resistance fields of size dims[0] x dims[1] x

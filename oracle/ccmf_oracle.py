@@ -26,9 +26,9 @@ Pins: every function here is checked by ``tests/test_oracle_*.py`` against
 something other than itself (brute-force index loops, dense linear algebra,
 closed forms derived from the discrete problem, an independent SciPy solver,
 bounds and a certified primal-dual bracket).  The iteration path of the
-adaptive penalty rule (the Barzilai-Borwein safeguard, READING 4) has no
-independent pin: "parity unpinned" for the penalty trajectory itself; its
-limit (geff) is pinned.
+adaptive penalty rules (the Barzilai-Borwein safeguard, READING 4) has no
+independent pin: "parity unpinned" for the penalty trajectory itself; the
+limit it converges to (geff) is pinned.
 """
 
 from __future__ import annotations
@@ -166,7 +166,9 @@ def energy(xi: np.ndarray, gamma: np.ndarray) -> float:
 # ---------------------------------------------------------------------------
 
 RHO_BB, RHO_CONST, RHO_LTD = "bb", "const", "ltd"
-RHO_WINDOW_LOW = 0.1     # READING 4: adaptive penalties accepted within [0.1 min gamma, max gamma]
+BB_MIN_CORRELATION = 0.2   # READING 4: reliability test of the Barzilai-Borwein estimate
+RHO_CLAMP = 1e6            # READING 4: adaptive penalties kept within [1/RHO_CLAMP, RHO_CLAMP] * rho0
+ETA0, K0 = 1.0, 100.0      # READING 4: rho^{k+1}/rho^k within [1/g_k, g_k], g_k = 1 + ETA0/(1 + k/K0)^2
 
 
 @dataclass
@@ -195,15 +197,28 @@ def rho_initial(gamma: np.ndarray) -> float:
     return float(pos.min())
 
 
-def rho_window(gamma: np.ndarray) -> tuple[float, float]:
-    """READING 4: the safeguard of the adaptive penalty.  A new value proposed by
-    the Barzilai-Borwein or Lorenz-Tran-Dinh formula is accepted only if it is
-    finite and lies in [RHO_WINDOW_LOW * min gamma, max gamma] (min over the
-    positive values); otherwise the previous penalty is kept."""
-    pos = gamma[gamma > 0]
-    if pos.size == 0:
-        return 1.0, 1.0
-    return RHO_WINDOW_LOW * float(pos.min()), float(pos.max())
+def ltd_penalty(v_new, e_new):
+    """Lorenz-Tran-Dinh scaling of Sec. 3.2: rho = |v|/|e| (None if undefined)."""
+    ne = inner(e_new, e_new)
+    nv = inner(v_new, v_new)
+    if ne > 0.0 and nv > 0.0:
+        return math.sqrt(nv / ne)
+    return None
+
+
+def bb_penalty(v_new, v, e_new, e):
+    """Barzilai-Borwein scaling of Sec. 3.2, rho = <dv, de>/|de|^2, with the
+    safeguard of READING 4: the estimate is used only where it is a reliable
+    curvature estimate, i.e. the correlation <dv, de>/(|dv| |de|) is at least
+    BB_MIN_CORRELATION; otherwise the Lorenz-Tran-Dinh scaling is used."""
+    dv = v_new - v
+    de = e_new - e
+    num = inner(dv, de)
+    den = inner(de, de)
+    dvv = inner(dv, dv)
+    if num > 0.0 and den > 0.0 and num >= BB_MIN_CORRELATION * math.sqrt(den * dvv):
+        return num / den
+    return ltd_penalty(v_new, e_new)
 
 
 def admm_step(e, v, rho, xibar, gamma, delta):
@@ -236,7 +251,7 @@ def admm_solve(gamma, xibar, tol=1e-4, delta=0.25, rule=RHO_BB, rho0=None,
         |e^k - xi^{k+1/2}|_{L2} <= tol |<v^k>|,
     checked on the pair (e^k, xi^{k+1/2}) of the same iteration (READING 5).
     Penalty rules of Sec. 3.2: Barzilai-Borwein (default), Lorenz-Tran-Dinh,
-    or constant rho^0; the adaptive rules are safeguarded by ``rho_window``.
+    or constant rho^0; the Barzilai-Borwein safeguard is ``bb_penalty``'s.
     """
     gamma = np.asarray(gamma, dtype=np.float64)
     if gamma.ndim != 3:
@@ -259,7 +274,6 @@ def admm_solve(gamma, xibar, tol=1e-4, delta=0.25, rule=RHO_BB, rho0=None,
     r0 = rho_initial(gamma) if rho0 is None else float(rho0)
     if not (r0 > 0.0 and math.isfinite(r0)):
         raise ValueError("rho0 must be positive and finite")
-    lo, hi = rho_window(gamma)
     rho = r0
     history = []
     # READING 7: if gamma vanishes identically, g = 0 on all of K and the first
@@ -287,24 +301,20 @@ def admm_solve(gamma, xibar, tol=1e-4, delta=0.25, rule=RHO_BB, rho0=None,
                 history=history)
 
         rho_new = rho
-        cand = None
         if rule == RHO_BB:
-            # Barzilai-Borwein scaling of Sec. 3.2.
-            de = e_new - e
-            num = inner(v_new - v, de)
-            den = inner(de, de)
-            if den > 0.0 and num > 0.0:
-                cand = num / den
+            cand = bb_penalty(v_new, v, e_new, e)
         elif rule == RHO_LTD:
-            # Lorenz-Tran-Dinh scaling of Sec. 3.2: rho = |v|/|e|.
-            ne = inner(e_new, e_new)
-            nv = inner(v_new, v_new)
-            if ne > 0.0 and nv > 0.0:
-                cand = math.sqrt(nv / ne)
-        elif rule != RHO_CONST:
+            cand = ltd_penalty(v_new, e_new)
+        elif rule == RHO_CONST:
+            cand = None
+        else:
             raise ValueError(f"unknown penalty rule {rule!r}")
-        if cand is not None and math.isfinite(cand) and lo <= cand <= hi:
-            rho_new = cand
+        if cand is not None and math.isfinite(cand) and cand > 0.0:
+            # READING 4: a summable relative variation of the penalty (the
+            # convergence condition of non-stationary Douglas-Rachford / ADMM)
+            g = 1.0 + ETA0 / (1.0 + k / K0) ** 2
+            rho_new = min(max(cand, rho / g), rho * g)
+            rho_new = min(max(rho_new, r0 / RHO_CLAMP), r0 * RHO_CLAMP)
 
         e, v, rho = e_new, v_new, rho_new
         k += 1

@@ -203,7 +203,8 @@ int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, i
               bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob) {
   constexpr int E = pow2::Plan<N>::E, TPL = N / E;
   int nlc = 16;
-  while (nlc > 1 && (nlc * TPL > 512 || (size_t)nlc * (N + 1) * 2 * sizeof(TC) > 65536)) nlc >>= 1;
+  constexpr int LP = line_pitch<N>();
+  while (nlc > 1 && (nlc * TPL > 512 || (size_t)(nlc * LP + N) * 2 * sizeof(TC) > 65536)) nlc >>= 1;
   while (nlc > 1 && 2 * (nlc >> 1) >= A.lines_total) nlc >>= 1;  // do not pad tiny line counts
   const int nl = 2 * nlc;
   int lognl = 0;
@@ -211,7 +212,13 @@ int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, i
   A.nl = nl;
   A.lognl = lognl;
   A.tiles_per_outer = (A.lines_total + nl - 1) / nl;
-  const size_t lds = (size_t)nlc * (N + 1) * 2 * sizeof(TC);
+  // vector loads/stores: rows need n3 % (16 / element size) == 0, columns an even n3
+  if (contig)
+    A.vec = (p->n[2] % (int)(16 / sizeof(TI)) == 0 && p->n[2] % (int)(16 / sizeof(TO)) == 0 && N >= 4) ? 1 : 0;
+  else
+    A.vec = (p->n[2] % 2 == 0) ? 1 : 0;
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) A.vec = 0;
+  const size_t lds = (size_t)(nlc * LP + N) * 2 * sizeof(TC);
   if (lds > 65536 || nlc * TPL > 512) return fail(CCMF_EINVAL, "transform length %d too large for the LDS tile", N);
   dim3 grid((unsigned)(outers * A.tiles_per_outer), (unsigned)count);
   dim3 block((unsigned)(nlc * TPL));
@@ -446,6 +453,12 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
   if (opt.delta == 0.0) opt.delta = 0.25;
   if (opt.max_iter == 0) opt.max_iter = 20000;
   if (opt.check_every == 0) opt.check_every = 32;
+  if (opt.bb_min_corr == 0.0) opt.bb_min_corr = 0.2;
+  if (opt.eta0 == 0.0) opt.eta0 = 1.0;
+  if (opt.k0 == 0.0) opt.k0 = 100.0;
+  if (!(opt.bb_min_corr >= 0.0 && opt.bb_min_corr <= 1.0)) return fail(CCMF_EINVAL, "bb_min_corr must lie in [0,1]");
+  if (!(opt.eta0 > 0.0) || !std::isfinite(opt.eta0)) return fail(CCMF_EINVAL, "eta0 must be positive");
+  if (!(opt.k0 > 0.0) || !std::isfinite(opt.k0)) return fail(CCMF_EINVAL, "k0 must be positive");
   if (!(opt.delta > 0.0 && opt.delta < 1.0)) return fail(CCMF_EINVAL, "delta must lie in (0,1)");
   if (opt.max_iter < 1) return fail(CCMF_EINVAL, "max_iter must be >= 1");
   if (opt.check_every < 1) return fail(CCMF_EINVAL, "check_every must be >= 1");
@@ -471,8 +484,11 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
     for (int c = 0; c < 3; ++c) P.xibar[c] = xi[3 * l + c] / nr;
     const bool any_pos = p->kmax[f] > 0.0;
     P.rho0 = opt.rho0 > 0.0 ? opt.rho0 : (any_pos ? p->kmin[f] : 1.0);
-    P.lo = any_pos ? 0.1 * p->kmin[f] : 1.0;
-    P.hi = any_pos ? p->kmax[f] : 1.0;
+    P.lo = P.rho0 * 1e-6;   // hard limits of the adaptive penalty
+    P.hi = P.rho0 * 1e6;
+    P.bb_corr = opt.bb_min_corr;
+    P.eta0 = opt.eta0;
+    P.k0 = opt.k0;
     P.rho = P.rho0;
     P.rho_prev = P.rho0;
     P.tol = tol;

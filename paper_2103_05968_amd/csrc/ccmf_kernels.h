@@ -30,8 +30,10 @@ enum {
   Q_BBD = 9,   // sum |e^{k+1} - e^k|^2
   Q_VV = 10,   // sum |v^{k+1}|^2
   Q_EE = 11,   // sum |e^{k+1}|^2
-  Q_DUAL = 12  // sum <A xibar, v^k>
+  Q_DUAL = 12,  // sum <A xibar, v^k>
+  Q_DVV = 13    // sum |v^{k+1} - v^k|^2
 };
+constexpr int kNQU = 14;  // partial sums in use
 
 // Per-problem scalars, device resident.  Written by the host before the first
 // iteration, afterwards only by k_finish (one thread).
@@ -39,6 +41,7 @@ struct Prob {
   double rho;       // rho^k, penalty of the running iteration
   double rho_prev;  // rho^{k-1}: e^k = (1 - alpha) z / rho_prev
   double rho0, lo, hi, tol, delta;
+  double bb_corr, eta0, k0;
   double xibar[3];
   double geff, res, mvn, dual;
   int32_t k;        // iteration index of the current state
@@ -197,9 +200,9 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
   T* znb = zn + (size_t)b * 6 * g.N;
   T* anb = an + (size_t)b * g.N;
 
-  double acc[13];
+  double acc[kNQU];
 #pragma unroll
-  for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kNQU; ++q) acc[q] = 0.0;
 
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int t0 = lb * g.tiles_per_blk;
@@ -244,7 +247,7 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
     acc[Q_E] += (double)(gm * sqrt(xn2));
     const T aln = ball_scale(sqrt(zn2), gm);
     const T cen = (T(1) - aln) * ir;
-    double bbn = 0.0, bbd = 0.0, vv = 0.0, ee = 0.0;
+    double bbn = 0.0, bbd = 0.0, vv = 0.0, ee = 0.0, dvv = 0.0;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       znb[(size_t)q * g.N + x] = zz[q];
@@ -254,6 +257,7 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
       const double de = en - (double)(ce * zo[q]);
       bbn += dv * de;
       bbd += de * de;
+      dvv += dv * dv;
       vv += vn * vn;
       ee += en * en;
     }
@@ -262,6 +266,7 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
     acc[Q_BBD] += bbd;
     acc[Q_VV] += vv;
     acc[Q_EE] += ee;
+    acc[Q_DVV] += dvv;
     double du = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) du += P.xibar[c] * (double)(al * (zo[c] + zo[c + 3]));
@@ -269,15 +274,15 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
   }
 
   // deterministic block reduction: wavefront shuffles, then fixed-order LDS sum
-  __shared__ double red[kThreads / 64][13];
+  __shared__ double red[kThreads / 64][kNQU];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 13; ++q) {
+  for (int q = 0; q < kNQU; ++q) {
     const double sq = wave_sum<T>(acc[q]);
     if (lane == 0) red[wv][q] = sq;
   }
   __syncthreads();
-  if (threadIdx.x < 13) {
+  if (threadIdx.x < kNQU) {
     double sq = 0.0;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) sq += red[w][threadIdx.x];
@@ -296,22 +301,22 @@ k_finish(int it, uint32_t N, int nparts, const double* __restrict__ partials,
   const int b = blockIdx.x;
   Prob& P = prob[b];
   if (P.done) return;
-  __shared__ double red[kThreads][13];
-  double acc[13];
+  __shared__ double red[kThreads][kNQU];
+  double acc[kNQU];
 #pragma unroll
-  for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kNQU; ++q) acc[q] = 0.0;
   const double* pp = partials + (size_t)b * nparts * kNQ;
   for (int i = threadIdx.x; i < nparts; i += kThreads) {
 #pragma unroll
-    for (int q = 0; q < 13; ++q) acc[q] += pp[(size_t)i * kNQ + q];
+    for (int q = 0; q < kNQU; ++q) acc[q] += pp[(size_t)i * kNQ + q];
   }
 #pragma unroll
-  for (int q = 0; q < 13; ++q) red[threadIdx.x][q] = acc[q];
+  for (int q = 0; q < kNQU; ++q) red[threadIdx.x][q] = acc[q];
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
 #pragma unroll
-      for (int q = 0; q < 13; ++q) red[threadIdx.x][q] += red[threadIdx.x + w][q];
+      for (int q = 0; q < kNQU; ++q) red[threadIdx.x][q] += red[threadIdx.x + w][q];
     }
     __syncthreads();
   }
@@ -342,16 +347,23 @@ k_finish(int it, uint32_t N, int nparts, const double* __restrict__ partials,
     P.k = it;
     return;
   }
+  // adaptive penalty of Sec. 3.2 with the safeguard (rule codes of include/ccmf.h)
   double cand = -1.0;
-  if (P.rule == 0) {  // Barzilai-Borwein
-    const double num = red[0][Q_BBN], den = red[0][Q_BBD];
-    if (den > 0.0 && num > 0.0) cand = num / den;
+  const double vv = red[0][Q_VV], ee = red[0][Q_EE];
+  const double ltd = (vv > 0.0 && ee > 0.0) ? sqrt(vv / ee) : -1.0;
+  if (P.rule == 0) {  // Barzilai-Borwein, reliable estimates only, else Lorenz-Tran-Dinh
+    const double num = red[0][Q_BBN], den = red[0][Q_BBD], dvv = red[0][Q_DVV];
+    cand = (num > 0.0 && den > 0.0 && num >= P.bb_corr * sqrt(den * dvv)) ? num / den : ltd;
   } else if (P.rule == 2) {  // Lorenz-Tran-Dinh
-    const double vv = red[0][Q_VV], ee = red[0][Q_EE];
-    if (vv > 0.0 && ee > 0.0) cand = sqrt(vv / ee);
+    cand = ltd;
   }
   double rn = P.rho;
-  if (cand >= P.lo && cand <= P.hi && isfinite(cand)) rn = cand;
+  if (cand > 0.0 && isfinite(cand)) {
+    const double q = 1.0 + (double)it / P.k0;
+    const double grow = 1.0 + P.eta0 / (q * q);   // summable relative variation
+    rn = fmin(fmax(cand, P.rho / grow), P.rho * grow);
+    rn = fmin(fmax(rn, P.lo), P.hi);
+  }
   P.rho_prev = P.rho;
   P.rho = rn;
   P.k = it + 1;
