@@ -31,6 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# Fabric traffic of the fused update kernel per launch and active problem on the 256^3 FP32
+# workload: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from the 2 GiB copy
+# kernel), see profiles/k_update_ud_fibres256_f32_traffic.md.  None once the kernel changes.
+K_UPDATE_TRAFFIC_C2 = (1045e6 + 472e6)
 
 
 def log(msg):
@@ -246,7 +250,8 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": (K_UPDATE_TRAFFIC_C2 if args.workload == "c2" else None),
+            "traffic_unit": "bytes per launch and active problem (rocprofv3 FETCH_SIZE, WRITE_SIZE)",
             "avg_launch_ms": avg_ms,
             "launches": launches,
             "bytes_per_launch_per_problem": bytes_per_problem,
