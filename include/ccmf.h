@@ -73,12 +73,19 @@ typedef struct {
   double eta0;         /* safeguard: |log(rho_{k+1}/rho_k)| <= log(1 + eta0/(1+k/k0)^2), a
                           summable variation; 0 selects 1.0                                  */
   double k0;           /* see eta0; 0 selects 100                                             */
+  int32_t eager;       /* nonzero: launch every kernel from the host; 0: capture one chunk of
+                          check_every iterations into a HIP graph once and replay it (also
+                          forced to eager when time_kernels is set)                          */
+  int32_t no_autotune; /* nonzero: skip the tile-width autotuner of the spectral passes (run
+                          once per plan and batch size, cached per process) and use defaults */
 } ccmf_options;
 
 /* Create a plan for n_fields crack-resistance fields of size dims[0] x dims[1] x
  * dims[2] (each >= 1, N = product < 2^31, each dim <= 2048 in F64 / 4096 in F32).
  * kappa_dev: device, [n_fields][N1][N2][N3] of the plan's dtype, finite and >= 0
- * (zeros are pores).  Copied into the plan.  stream: hipStream_t (NULL = default).
+ * (zeros are pores).  Copied into the plan.  stream: hipStream_t; NULL makes the plan
+ * create its own blocking stream (ordered with the null stream), since the null
+ * stream cannot be captured into a HIP graph.
  * Errors: CCMF_EINVAL for bad sizes/dtype or a negative / non-finite kappa entry. */
 int ccmf_setup(ccmf_plan* out, const int64_t dims[3], int64_t n_fields, int32_t dtype,
                const void* kappa_dev, void* stream);

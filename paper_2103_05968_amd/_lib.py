@@ -27,7 +27,8 @@ class Options(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("rho0", ctypes.c_double), ("rule", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("time_kernels", ctypes.c_int32), ("bb_min_corr", ctypes.c_double),
-                ("eta0", ctypes.c_double), ("k0", ctypes.c_double)]
+                ("eta0", ctypes.c_double), ("k0", ctypes.c_double), ("eager", ctypes.c_int32),
+                ("no_autotune", ctypes.c_int32)]
 
 
 class CcmfError(RuntimeError):

@@ -87,13 +87,14 @@ class Plan:
               rule: str = "bb", rho0: float = 0.0, max_iter: int = 20000, check_every: int = 32,
               want_phi: bool = False, want_flux: bool = False, time_kernels: bool = False,
               raise_not_converged: bool = False, bb_min_corr: float = 0.0, eta0: float = 0.0,
-              k0: float = 0.0) -> SolveResult:
+              k0: float = 0.0, eager: bool = False, autotune: bool = True) -> SolveResult:
         xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(-1, 3))
         L = xi.shape[0]
         B = self.n_fields * L
         opt = _lib.Options(delta=delta, rho0=rho0, rule=_lib.RULES[rule], max_iter=max_iter,
                            check_every=check_every, time_kernels=int(bool(time_kernels)),
-                           bb_min_corr=bb_min_corr, eta0=eta0, k0=k0)
+                           bb_min_corr=bb_min_corr, eta0=eta0, k0=k0, eager=int(bool(eager)),
+                           no_autotune=int(not autotune))
         geff = np.zeros(B)
         iters = np.zeros(B, dtype=np.int32)
         res = np.zeros(B)

@@ -5,11 +5,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -90,6 +94,7 @@ struct ccmf_plan_s {
   uint32_t N = 1;
   int64_t nfields = 0;
   hipStream_t stream = nullptr;
+  bool own_stream = false;  // created by the plan when the caller passes the null stream
   int device = 0;
   void* kap = nullptr;
   std::vector<double> kmin, kmax;  // per field: smallest positive, largest
@@ -106,7 +111,18 @@ struct ccmf_plan_s {
   Prob* prob = nullptr;    // device
   Prob* probh = nullptr;   // pinned host
   bool solved = false;
-  int upd_blocks = 0, tiles_per_blk = 0;
+  int upd_blocks = 0, tiles_per_blk = 0, tpp = 0;
+
+  // autotuned tile widths (complex lines per block) of the five Hartley passes
+  // (0 forward k, 1 forward j, 2 fused i, 3 inverse j, 4 inverse k); 0 = rule of thumb
+  int nlc_hint[5] = {0, 0, 0, 0, 0};
+  int64_t tuned_B = 0;
+
+  // captured chunk of iterations (HIP graph), valid for the current state buffers
+  hipGraphExec_t gexec = nullptr;
+  int graph_iters = 0;
+  Prob* flagsh[2] = {nullptr, nullptr};  // pinned copies of the scalars, one per chunk in flight
+  hipEvent_t fev[2] = {nullptr, nullptr};
 
   // kernel timing
   std::vector<hipEvent_t> ev;
@@ -124,8 +140,21 @@ struct ccmf_plan_s {
     }
     free_state();
     for (auto e : ev) hipEventDestroy(e);
+    for (int q = 0; q < 2; ++q)
+      if (fev[q]) hipEventDestroy(fev[q]);
+    if (own_stream) hipStreamDestroy(stream);
+  }
+  void drop_graph() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    graph_iters = 0;
   }
   void free_state() {
+    drop_graph();
+    for (int q = 0; q < 2; ++q) {
+      if (flagsh[q]) hipHostFree(flagsh[q]);
+      flagsh[q] = nullptr;
+    }
     for (int p = 0; p < 2; ++p) {
       hipFree(z[p]);
       hipFree(a[p]);
@@ -158,6 +187,7 @@ Geo make_geo(const ccmf_plan_s* p) {
   g.nloads = (int32_t)p->nloads;
   g.tiles = (int32_t)((p->N + kThreads - 1) / kThreads);
   g.tiles_per_blk = p->tiles_per_blk;
+  g.tpp = p->tpp;
   return g;
 }
 
@@ -200,12 +230,16 @@ bool is_pow2_len(int n) { return n >= 2 && n <= 2048 && (n & (n - 1)) == 0; }
 // block, NLC * TPL <= 512 threads, padded LDS tile within 64 KiB.
 template <typename TI, typename TO, typename TC, int N>
 int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
-              bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob) {
+              bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob, int kind) {
   constexpr int E = pow2::Plan<N>::E, TPL = N / E;
-  int nlc = 16;
   constexpr int LP = line_pitch<N>();
-  while (nlc > 1 && (nlc * TPL > 512 || (size_t)(nlc * LP + N) * 2 * sizeof(TC) > 65536)) nlc >>= 1;
-  while (nlc > 1 && 2 * (nlc >> 1) >= A.lines_total) nlc >>= 1;  // do not pad tiny line counts
+  int nlc = 16;
+  if (kind >= 0 && p->nlc_hint[kind] > 0) {
+    nlc = p->nlc_hint[kind];
+  } else {
+    while (nlc > 1 && (nlc * TPL > 512 || (size_t)(nlc * LP + N) * 2 * sizeof(TC) > 65536)) nlc >>= 1;
+    while (nlc > 1 && 2 * (nlc >> 1) >= A.lines_total) nlc >>= 1;  // do not pad tiny line counts
+  }
   const int nl = 2 * nlc;
   int lognl = 0;
   while ((1 << lognl) < nl) ++lognl;
@@ -241,7 +275,7 @@ int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, i
 // compute in TC, store TO to `out` (same layout, may alias).
 template <typename TI, typename TO, typename TC>
 int launch_hartley(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, int axis, bool middle,
-                   const Prob* prob) {
+                   const Prob* prob, int kind = -1) {
   const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
   const Axis& ax = p->ax[axis];
   DhtArgs A;
@@ -284,17 +318,17 @@ int launch_hartley(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, int axi
   const TC* s3 = reinterpret_cast<const TC*>(p->ax[2].s[q]);
   if (is_pow2_len(A.n)) {
     switch (A.n) {
-      case 2: return launch_p2<TI, TO, TC, 2>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 4: return launch_p2<TI, TO, TC, 4>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 8: return launch_p2<TI, TO, TC, 8>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 16: return launch_p2<TI, TO, TC, 16>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 32: return launch_p2<TI, TO, TC, 32>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 64: return launch_p2<TI, TO, TC, 64>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 128: return launch_p2<TI, TO, TC, 128>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 256: return launch_p2<TI, TO, TC, 256>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 512: return launch_p2<TI, TO, TC, 512>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 1024: return launch_p2<TI, TO, TC, 1024>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
-      case 2048: return launch_p2<TI, TO, TC, 2048>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob);
+      case 2: return launch_p2<TI, TO, TC, 2>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 4: return launch_p2<TI, TO, TC, 4>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 8: return launch_p2<TI, TO, TC, 8>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 16: return launch_p2<TI, TO, TC, 16>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 32: return launch_p2<TI, TO, TC, 32>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 64: return launch_p2<TI, TO, TC, 64>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 128: return launch_p2<TI, TO, TC, 128>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 256: return launch_p2<TI, TO, TC, 256>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 512: return launch_p2<TI, TO, TC, 512>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 1024: return launch_p2<TI, TO, TC, 1024>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 2048: return launch_p2<TI, TO, TC, 2048>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
       default: break;
     }
   }
@@ -324,11 +358,13 @@ int launch_hartley(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, int axi
 template <typename T>
 int launch_laplace(ccmf_plan_s* p, T* r, double* phi, int64_t count, const Prob* prob) {
   int rc;
-  if (p->n[2] > 1 && (rc = launch_hartley<T, T, T>(p, r, r, count, 2, false, prob))) return rc;
-  if (p->n[1] > 1 && (rc = launch_hartley<T, T, T>(p, r, r, count, 1, false, prob))) return rc;
-  if ((rc = launch_hartley<T, double, double>(p, r, phi, count, 0, true, prob))) return rc;
-  if (p->n[1] > 1 && (rc = launch_hartley<double, double, double>(p, phi, phi, count, 1, false, prob))) return rc;
-  if (p->n[2] > 1 && (rc = launch_hartley<double, double, double>(p, phi, phi, count, 2, false, prob))) return rc;
+  if (p->n[2] > 1 && (rc = launch_hartley<T, T, T>(p, r, r, count, 2, false, prob, 0))) return rc;
+  if (p->n[1] > 1 && (rc = launch_hartley<T, T, T>(p, r, r, count, 1, false, prob, 1))) return rc;
+  if ((rc = launch_hartley<T, double, double>(p, r, phi, count, 0, true, prob, 2))) return rc;
+  if (p->n[1] > 1 && (rc = launch_hartley<double, double, double>(p, phi, phi, count, 1, false, prob, 3)))
+    return rc;
+  if (p->n[2] > 1 && (rc = launch_hartley<double, double, double>(p, phi, phi, count, 2, false, prob, 4)))
+    return rc;
   return CCMF_OK;
 }
 
@@ -366,12 +402,26 @@ int ensure_state(ccmf_plan_s* p, int64_t nloads) {
   const int64_t B = p->nfields * nloads;
   p->nloads = nloads;
   // fused update: up to 2048 blocks per problem, independent of the batch size,
-  // so the FP64 reduction order (and every result) is the same batched or alone
+  // so the FP64 reduction order (and every result) is the same batched or alone.
+  // With whole tiles per i-plane a block walks planes (see tile_of).
   const int tiles = (int)((p->N + kThreads - 1) / kThreads);
-  int want = std::min(tiles, 2048);
-  if (want > 8) want &= ~7;
-  p->tiles_per_blk = (tiles + want - 1) / want;
-  p->upd_blocks = (tiles + p->tiles_per_blk - 1) / p->tiles_per_blk;
+  const int64_t n23 = (int64_t)p->n[1] * p->n[2];
+  p->tpp = 0;
+  if (n23 % kThreads == 0) {
+    const int tpp = (int)(n23 / kThreads);
+    int want = std::min(tiles, 2048);
+    int cpb = std::max(1, (want + tpp - 1) / tpp);          // i-chunks per problem
+    cpb = std::min(cpb, p->n[0]);
+    p->tiles_per_blk = (p->n[0] + cpb - 1) / cpb;            // planes per block
+    cpb = (p->n[0] + p->tiles_per_blk - 1) / p->tiles_per_blk;
+    p->upd_blocks = cpb * tpp;
+    p->tpp = tpp;
+  } else {
+    int want = std::min(tiles, 2048);
+    if (want > 8) want &= ~7;
+    p->tiles_per_blk = (tiles + want - 1) / want;
+    p->upd_blocks = (tiles + p->tiles_per_blk - 1) / p->tiles_per_blk;
+  }
   if (B == p->B && p->z[0] != nullptr) return CCMF_OK;
   p->free_state();
   const size_t N = p->N;
@@ -388,6 +438,10 @@ int ensure_state(ccmf_plan_s* p, int64_t nloads) {
   HIP_TRY(hipMalloc(&p->partials, (size_t)B * p->upd_blocks * kNQ * sizeof(double)));
   HIP_TRY(hipMalloc(&p->prob, (size_t)B * sizeof(Prob)));
   HIP_TRY(hipHostMalloc((void**)&p->probh, (size_t)B * sizeof(Prob), hipHostMallocDefault));
+  for (int q = 0; q < 2; ++q) {
+    HIP_TRY(hipHostMalloc((void**)&p->flagsh[q], (size_t)B * sizeof(Prob), hipHostMallocDefault));
+    if (!p->fev[q]) HIP_TRY(hipEventCreateWithFlags(&p->fev[q], hipEventDisableTiming));
+  }
   p->B = B;
   return CCMF_OK;
 }
@@ -437,9 +491,81 @@ int run_iteration(ccmf_plan_s* p, int it, bool timed) {
                      p->partials, p->prob);
   HIP_LAUNCH_CHECK();
   if (timed && (rc = record_event(p, &e1))) return rc;
-  hipLaunchKernelGGL(k_finish, dim3((unsigned)p->B), dim3(kThreads), 0, p->stream, it, p->N,
-                     p->upd_blocks, p->partials, p->prob, (double*)nullptr, 0);
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)p->B), dim3(kThreads), 0, p->stream, p->N, p->upd_blocks,
+                     p->partials, p->prob, (double*)nullptr, 0);
   HIP_LAUNCH_CHECK();
+  return CCMF_OK;
+}
+
+// Autotuner of the Hartley tile widths: for each of the five passes, time every
+// feasible width (1..16 complex lines per block) on the plan's own buffers for
+// the current batch and keep the fastest.  The width only changes how lines are
+// grouped into blocks, never the arithmetic of a line, so results do not depend
+// on it.  Winners are cached per (grid, dtype, batch) for the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int64_t>, std::array<int, 5>> g_tune_cache;
+
+template <typename T>
+int run_pass(ccmf_plan_s* p, int kind) {
+  T* r = reinterpret_cast<T*>(p->r);
+  double* phi = p->phi;
+  switch (kind) {
+    case 0: return launch_hartley<T, T, T>(p, r, r, p->B, 2, false, nullptr, 0);
+    case 1: return launch_hartley<T, T, T>(p, r, r, p->B, 1, false, nullptr, 1);
+    case 2: return launch_hartley<T, double, double>(p, r, phi, p->B, 0, true, nullptr, 2);
+    case 3: return launch_hartley<double, double, double>(p, phi, phi, p->B, 1, false, nullptr, 3);
+    default: return launch_hartley<double, double, double>(p, phi, phi, p->B, 2, false, nullptr, 4);
+  }
+}
+
+template <typename T>
+int autotune(ccmf_plan_s* p) {
+  const auto key = std::make_tuple(p->n[0], p->n[1], p->n[2], p->dt, p->B);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      for (int k = 0; k < 5; ++k) p->nlc_hint[k] = it->second[k];
+      p->tuned_B = p->B;
+      return CCMF_OK;
+    }
+  }
+  HIP_TRY(hipMemsetAsync(p->phi, 0, (size_t)p->B * p->N * sizeof(double), p->stream));
+  if (p->r != (void*)p->phi) HIP_TRY(hipMemsetAsync(p->r, 0, (size_t)p->B * p->N * sizeof(T), p->stream));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::array<int, 5> best{};
+  const bool present[5] = {p->n[2] > 1, p->n[1] > 1, true, p->n[1] > 1, p->n[2] > 1};
+  for (int kind = 0; kind < 5; ++kind) {
+    best[kind] = 0;
+    if (!present[kind] || !is_pow2_len(p->ax[kind == 2 ? 0 : (kind == 1 || kind == 3) ? 1 : 2].n)) continue;
+    float best_ms = 1e30f;
+    for (int nlc = 1; nlc <= 16; nlc <<= 1) {
+      p->nlc_hint[kind] = nlc;
+      if (run_pass<T>(p, kind) != CCMF_OK) continue;  // infeasible width (LDS or threads)
+      hipEventRecord(e0, p->stream);
+      for (int rep = 0; rep < 3; ++rep) run_pass<T>(p, kind);
+      hipEventRecord(e1, p->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) break;
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best[kind] = nlc;
+      }
+    }
+    p->nlc_hint[kind] = best[kind];
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(CCMF_EDEVICE, "autotune: %s", hipGetErrorString(e));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  p->tuned_B = p->B;
   return CCMF_OK;
 }
 
@@ -475,6 +601,14 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
   int rc = ensure_state(p, nloads);
   if (rc) return rc;
   p->solved = false;
+  if (p->tuned_B != p->B) {
+    if (opt.no_autotune) {
+      for (int k = 0; k < 5; ++k) p->nlc_hint[k] = 0;
+      p->tuned_B = 0;
+    } else if ((rc = autotune<T>(p))) {
+      return rc;
+    }
+  }
 
   for (int64_t b = 0; b < p->B; ++b) {
     const int64_t f = b / nloads, l = b % nloads;
@@ -508,15 +642,58 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
     HIP_LAUNCH_CHECK();
   }
   p->ev_used = 0;
-  bool all_done = false;
-  for (int it = 0; it < opt.max_iter && !all_done; ++it) {
-    if ((rc = run_iteration<T>(p, it, opt.time_kernels != 0))) return rc;
-    if ((it + 1) % opt.check_every == 0 || it + 1 == opt.max_iter) {
-      HIP_TRY(hipMemcpyAsync(p->probh, p->prob, (size_t)p->B * sizeof(Prob), hipMemcpyDeviceToHost, p->stream));
-      HIP_TRY(hipStreamSynchronize(p->stream));
-      all_done = true;
-      for (int64_t b = 0; b < p->B; ++b) all_done = all_done && p->probh[b].done != 0;
-      if (opt.time_kernels && (rc = harvest_events(p))) return rc;
+  const bool eager = opt.eager != 0 || opt.time_kernels != 0;
+  if (eager) {
+    bool all_done = false;
+    for (int it = 0; it < opt.max_iter && !all_done; ++it) {
+      if ((rc = run_iteration<T>(p, it, opt.time_kernels != 0))) return rc;
+      if ((it + 1) % opt.check_every == 0 || it + 1 == opt.max_iter) {
+        HIP_TRY(hipMemcpyAsync(p->probh, p->prob, (size_t)p->B * sizeof(Prob), hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        all_done = true;
+        for (int64_t b = 0; b < p->B; ++b) all_done = all_done && p->probh[b].done != 0;
+        if (opt.time_kernels && (rc = harvest_events(p))) return rc;
+      }
+    }
+  } else {
+    // One chunk of K iterations (K even, so the ping-pong parity repeats) is
+    // captured once into a HIP graph and replayed; the kernels read the iteration
+    // index from the device and finished problems return at once.  The host
+    // keeps one chunk in flight and inspects the flags of the previous one.
+    const int K = (opt.check_every + 1) & ~1;
+    if (!p->gexec || p->graph_iters != K) {
+      p->drop_graph();
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+      int crc = CCMF_OK;
+      for (int j = 0; j < K && crc == CCMF_OK; ++j) crc = run_iteration<T>(p, j, false);
+      hipError_t ce = hipStreamEndCapture(p->stream, &graph);
+      if (crc) {
+        if (graph) hipGraphDestroy(graph);
+        return crc;
+      }
+      if (ce != hipSuccess) return fail(CCMF_EDEVICE, "graph capture: %s", hipGetErrorString(ce));
+      ce = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (ce != hipSuccess) {
+        p->gexec = nullptr;
+        return fail(CCMF_EDEVICE, "graph instantiate: %s", hipGetErrorString(ce));
+      }
+      p->graph_iters = K;
+    }
+    const int chunks = (opt.max_iter + K - 1) / K;
+    for (int c = 0; c < chunks; ++c) {
+      HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
+      const int slot = c & 1;
+      HIP_TRY(hipMemcpyAsync(p->flagsh[slot], p->prob, (size_t)p->B * sizeof(Prob), hipMemcpyDeviceToHost,
+                             p->stream));
+      HIP_TRY(hipEventRecord(p->fev[slot], p->stream));
+      if (c >= 1) {
+        HIP_TRY(hipEventSynchronize(p->fev[slot ^ 1]));
+        bool all_done = true;
+        for (int64_t b = 0; b < p->B; ++b) all_done = all_done && p->flagsh[slot ^ 1][b].done != 0;
+        if (all_done) break;
+      }
     }
   }
   HIP_TRY(hipMemcpyAsync(p->probh, p->prob, (size_t)p->B * sizeof(Prob), hipMemcpyDeviceToHost, p->stream));
@@ -596,6 +773,16 @@ int ccmf_setup(ccmf_plan* out, const int64_t dims[3], int64_t n_fields, int32_t 
   p->N = (uint32_t)N;
   p->nfields = n_fields;
   p->stream = reinterpret_cast<hipStream_t>(stream);
+  if (p->stream == nullptr) {
+    // the null stream cannot be captured into a graph: use a blocking stream of
+    // our own (default priority), ordered with the null stream by its semantics
+    hipError_t se = hipStreamCreate(&p->stream);
+    if (se != hipSuccess) {
+      delete p;
+      return fail(CCMF_EDEVICE, "stream creation: %s", hipGetErrorString(se));
+    }
+    p->own_stream = true;
+  }
   for (int c = 0; c < 3; ++c) {
     if ((size_t)2 * 2 * p->n[c] * p->esz > 65536) {
       delete p;

@@ -365,8 +365,10 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
   TC* Lr = reinterpret_cast<TC*>(smem_raw);
   const int c = threadIdx.x / TPL, t = threadIdx.x & (TPL - 1);
 
-  const int outer = blockIdx.x / A.tiles_per_outer;
-  const int lt = blockIdx.x - outer * A.tiles_per_outer;
+  // XCD-contiguous tiles: neighbouring tiles share the 128-byte lines of a row
+  const int bx = xcd_remap(blockIdx.x, gridDim.x);
+  const int outer = bx / A.tiles_per_outer;
+  const int lt = bx - outer * A.tiles_per_outer;
   const int line0 = lt * nl;
   const int nvalid = min(nl, A.lines_total - line0);
   const size_t off = (size_t)b * A.field_stride + (size_t)outer * A.os + (size_t)line0 * A.ls;

@@ -55,7 +55,21 @@ struct Geo {
   int32_t nloads;
   int32_t tiles;        // ceil(N / kThreads)
   int32_t tiles_per_blk;
+  int32_t tpp;          // tiles per i-plane when n2*n3 % kThreads == 0, else 0
 };
+
+// Tile visited by logical block lb at step m.  With whole tiles per plane, a
+// block walks tiles_per_blk consecutive planes at one in-plane tile, so the
+// i-1 and i+1 rows it reads are its own previous and next steps; adjacent
+// logical blocks take adjacent in-plane tiles (the j neighbours).  Otherwise
+// a block takes tiles_per_blk consecutive tiles.
+__device__ __forceinline__ int tile_of(const Geo& g, int lb, int m) {
+  if (g.tpp > 0) {
+    const int u = lb % g.tpp, c = lb / g.tpp;
+    return (c * g.tiles_per_blk + m) * g.tpp + u;
+  }
+  return lb * g.tiles_per_blk + m;
+}
 
 __device__ __forceinline__ int xcd_remap(int w, int G) {
   // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; give
@@ -144,9 +158,9 @@ k_div(Geo g, const T* __restrict__ z, const T* __restrict__ a, T* __restrict__ r
   const T* ab = a + (size_t)b * g.N;
   T* rb = r + (size_t)b * g.N;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int t0 = lb * g.tiles_per_blk;
-  const int t1 = min(t0 + g.tiles_per_blk, g.tiles);
-  for (int t = t0; t < t1; ++t) {
+  for (int m = 0; m < g.tiles_per_blk; ++m) {
+    const int t = tile_of(g, lb, m);
+    if (t >= g.tiles) break;
     const uint32_t x = (uint32_t)t * kThreads + threadIdx.x;
     if (x >= g.N) continue;
     const Nbr nb = neighbours(g, x);
@@ -205,9 +219,9 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
   for (int q = 0; q < kNQU; ++q) acc[q] = 0.0;
 
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int t0 = lb * g.tiles_per_blk;
-  const int t1 = min(t0 + g.tiles_per_blk, g.tiles);
-  for (int t = t0; t < t1; ++t) {
+  for (int m = 0; m < g.tiles_per_blk; ++m) {
+    const int t = tile_of(g, lb, m);
+    if (t >= g.tiles) break;
     const uint32_t x = (uint32_t)t * kThreads + threadIdx.x;
     if (x >= g.N) continue;
     const Nbr nb = neighbours(g, x);
@@ -296,11 +310,14 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
 // host round trip).  One block per problem.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads)
-k_finish(int it, uint32_t N, int nparts, const double* __restrict__ partials,
-         Prob* __restrict__ prob, double* __restrict__ hist, int hist_len) {
+k_finish(uint32_t N, int nparts, const double* __restrict__ partials, Prob* __restrict__ prob,
+         double* __restrict__ hist, int hist_len) {
   const int b = blockIdx.x;
   Prob& P = prob[b];
   if (P.done) return;
+  // the iteration index lives on the device, so a captured chunk of iterations
+  // can be replayed unchanged
+  const int it = P.k;
   __shared__ double red[kThreads][kNQU];
   double acc[kNQU];
 #pragma unroll

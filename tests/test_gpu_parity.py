@@ -157,6 +157,19 @@ def test_batched_equals_single(dtype):
             assert s.iterations[0, 0] == batched.iterations[f, l]
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_graph_replay_equals_eager_launches(dtype):
+    banner(f"graph vs eager {dtype}")
+    g = M.boolean_spheres((20, 16, 12), 3.0, 0.2, 5.0, 1.0, seed=9)
+    p = plan_of(g, dtype)
+    loads = [(1, 0, 0), (0.36, 0.48, 0.8)]
+    for K, tol in [(7, 1e-300), (400, 1e-5)]:
+        a = p.solve(loads, tol=tol, max_iter=K, check_every=6, want_phi=True)
+        b = p.solve(loads, tol=tol, max_iter=K, check_every=6, want_phi=True, eager=True)
+        assert np.array_equal(a.geff, b.geff) and np.array_equal(a.iterations, b.iterations)
+        assert torch.equal(a.phi, b.phi)
+
+
 def test_gradient_fp64_matches_oracle_and_fd():
     banner("gradient fp64")
     rng = np.random.default_rng(3)
