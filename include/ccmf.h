@@ -113,6 +113,15 @@ int ccmf_solve(ccmf_plan p, const double* xi, int64_t n_loads, double tol, const
  * dL_dgeff: host, [B].  dkappa_dev: device out, [n_fields][N] of the plan's dtype. */
 int ccmf_grad_kappa(ccmf_plan p, const double* dL_dgeff, void* dkappa_dev);
 
+/* Certified lower bound of geff for every problem of the last solve (strong duality
+ * of Sec. 2.1 for the max-flow form eq:CCMF_FFT_problemA): with the face flux y = A* v^k
+ * of the stopping iterate, its divergence-free part y_df = y - grad^+ L^dagger div^- y
+ * (same spectral solve) and sigma = max over gamma > 0 of |A y_df| / gamma, the flux
+ * y_df / max(1, sigma) is feasible, so cert = <xibar, y> / max(1, sigma) <= geff.
+ * cert: host out [B]; -inf when a voxel with gamma = 0 carries flux.  sigma: host out
+ * [B] (nullable).  Allocates scratch (N doubles per problem) for the duration of the call. */
+int ccmf_certificate(ccmf_plan p, double* cert, double* sigma);
+
 /* Average device duration (ms) of the fused update kernel over the launches timed
  * since the last call (options.time_kernels), the number of launches, and the
  * kernel's algorithmic HBM bytes per launch per problem.  Resets the counters. */

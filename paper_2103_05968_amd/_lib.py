@@ -19,7 +19,7 @@ CCMF_F64 = 0
 CCMF_F32 = 1
 RULES = {"bb": 0, "const": 1, "ltd": 2}
 
-EXPORTS = ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_kernel_times", "ccmf_laplace_pinv",
+EXPORTS = ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_certificate", "ccmf_kernel_times", "ccmf_laplace_pinv",
            "ccmf_hartley_axis", "ccmf_stream_copy", "ccmf_destroy", "ccmf_last_error")
 
 
@@ -54,13 +54,15 @@ def load():
     lib.ccmf_solve.argtypes = [vp, pd, i64, dbl, ctypes.POINTER(Options), pd, pi32, pd, pd, vp, vp]
     lib.ccmf_grad_kappa.argtypes = [vp, pd, vp]
     lib.ccmf_kernel_times.argtypes = [vp, pd, pi64, pd]
+    lib.ccmf_certificate.argtypes = [vp, pd, pd]
     lib.ccmf_laplace_pinv.argtypes = [vp, vp, vp, i64]
     lib.ccmf_hartley_axis.argtypes = [vp, vp, i64, i32]
     lib.ccmf_stream_copy.argtypes = [vp, vp, i64, vp]
     lib.ccmf_destroy.argtypes = [vp]
     lib.ccmf_destroy.restype = None
     lib.ccmf_last_error.restype = ctypes.c_char_p
-    for name in ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_kernel_times", "ccmf_laplace_pinv",
+    for name in ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_certificate", "ccmf_kernel_times",
+                 "ccmf_laplace_pinv",
                  "ccmf_hartley_axis", "ccmf_stream_copy"):
         getattr(lib, name).restype = i32
     _lib = lib

@@ -128,6 +128,16 @@ class Plan:
                                                  _dptr(out)))
         return out
 
+    def certificate(self):
+        """(cert, sigma) per (field, load) of the last solve: cert <= geff_true <= geff."""
+        B = self.n_fields * self.n_loads
+        cert = np.zeros(B)
+        sig = np.zeros(B)
+        dp = ctypes.POINTER(ctypes.c_double)
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.ccmf_certificate(self._h, cert.ctypes.data_as(dp), sig.ctypes.data_as(dp)))
+        return cert.reshape(self.n_fields, -1), sig.reshape(self.n_fields, -1)
+
     def kernel_times(self):
         """(average ms, launches, algorithmic bytes per launch and problem) of the fused update kernel."""
         avg = ctypes.c_double()

@@ -749,6 +749,65 @@ int grad_impl(ccmf_plan_s* p, const double* dl, void* dkap) {
   return CCMF_OK;
 }
 
+template <typename T>
+int certificate_impl(ccmf_plan_s* p, double* cert, double* sigma) {
+  if (!p->solved) return fail(CCMF_ESTATE, "ccmf_certificate needs a preceding ccmf_solve");
+  if (!cert) return fail(CCMF_EINVAL, "null argument");
+  const Geo g = make_geo(p);
+  const size_t n = (size_t)p->B * p->N;
+  double* phic = nullptr;
+  T* rc = nullptr;
+  double* part = nullptr;
+  const int blocks = (int)std::min<uint64_t>(1024, (p->N + kThreads - 1) / kThreads);
+  hipError_t e = hipMalloc(&phic, n * sizeof(double));
+  if (e == hipSuccess) {
+    if (sizeof(T) == 8)
+      rc = reinterpret_cast<T*>(phic);
+    else
+      e = hipMalloc(&rc, n * sizeof(T));
+  }
+  if (e == hipSuccess) e = hipMalloc(&part, (size_t)p->B * blocks * 3 * sizeof(double));
+  int rc_status = CCMF_OK;
+  std::vector<double> h((size_t)p->B * blocks * 3);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL((k_cert_r<T>), dim3(blocks, (unsigned)p->B), dim3(kThreads), 0, p->stream, g,
+                       reinterpret_cast<const T*>(p->z[0]), reinterpret_cast<const T*>(p->z[1]),
+                       reinterpret_cast<const T*>(p->a[0]), reinterpret_cast<const T*>(p->a[1]), rc, p->prob);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) rc_status = launch_laplace<T>(p, rc, phic, p->B, nullptr);
+  if (e == hipSuccess && rc_status == CCMF_OK) {
+    hipLaunchKernelGGL((k_cert_sigma<T>), dim3(blocks, (unsigned)p->B), dim3(kThreads), 0, p->stream, g,
+                       reinterpret_cast<const T*>(p->kap), reinterpret_cast<const T*>(p->z[0]),
+                       reinterpret_cast<const T*>(p->z[1]), reinterpret_cast<const T*>(p->a[0]),
+                       reinterpret_cast<const T*>(p->a[1]), phic, part, p->prob);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  }
+  if ((void*)rc != (void*)phic) hipFree(rc);
+  hipFree(phic);
+  hipFree(part);
+  if (rc_status) return rc_status;
+  if (e != hipSuccess) return fail(CCMF_EDEVICE, "certificate: %s", hipGetErrorString(e));
+  for (int64_t b = 0; b < p->B; ++b) {
+    double mx = 0.0, bad = 0.0, yn = 0.0;
+    for (int bl = 0; bl < blocks; ++bl) {
+      const double* o = &h[((size_t)b * blocks + bl) * 3];
+      mx = std::max(mx, o[0]);
+      bad = std::max(bad, o[1]);
+      yn = std::max(yn, o[2]);
+    }
+    const double dual = p->probh[b].dual;
+    // a pore carrying flux (beyond rounding) leaves no feasible scaling
+    const bool undefined = bad > 1e-9 * std::max(1.0, yn);
+    cert[b] = undefined ? -INFINITY : dual / std::max(1.0, mx);
+    if (sigma) sigma[b] = undefined ? INFINITY : mx;
+  }
+  return CCMF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -832,6 +891,11 @@ int ccmf_solve(ccmf_plan p, const double* xi, int64_t n_loads, double tol, const
 int ccmf_grad_kappa(ccmf_plan p, const double* dL_dgeff, void* dkappa_dev) {
   if (!p) return fail(CCMF_EINVAL, "null plan");
   return p->dt == CCMF_F64 ? grad_impl<double>(p, dL_dgeff, dkappa_dev) : grad_impl<float>(p, dL_dgeff, dkappa_dev);
+}
+
+int ccmf_certificate(ccmf_plan p, double* cert, double* sigma) {
+  if (!p) return fail(CCMF_EINVAL, "null plan");
+  return p->dt == CCMF_F64 ? certificate_impl<double>(p, cert, sigma) : certificate_impl<float>(p, cert, sigma);
 }
 
 int ccmf_kernel_times(ccmf_plan p, double* avg_ms, int64_t* count, double* bytes_per_launch) {

@@ -485,6 +485,91 @@ k_kappa_stats(const T* __restrict__ kap, uint32_t N, double* __restrict__ out) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Certified dual bound (strong duality, Sec. 2.1; max-flow form eq:CCMF_FFT_problemA).
+// y = A* v is a face flux; y_df = y - grad^+ L^dagger div^- y is divergence free with
+// the same mean, so y_df / max(1, sigma), sigma = max |A y_df| / gamma, is feasible
+// and <xibar, y>/max(1, sigma) <= geff.  k_cert_r forms div^- y, k_cert_sigma the max.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_cert_r(Geo g, const T* __restrict__ z0, const T* __restrict__ z1, const T* __restrict__ a0,
+         const T* __restrict__ a1, T* __restrict__ r, const Prob* __restrict__ prob) {
+  const int b = blockIdx.y;
+  const int par = prob[b].k & 1;
+  const T* zb = (par ? z1 : z0) + (size_t)b * 6 * g.N;
+  const T* ab = (par ? a1 : a0) + (size_t)b * g.N;
+  T* rb = r + (size_t)b * g.N;
+  for (uint32_t x = blockIdx.x * kThreads + threadIdx.x; x < g.N; x += gridDim.x * kThreads) {
+    const Nbr nb = neighbours(g, x);
+    const T ax = ab[x];
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // y_c[x] - y_c[x - e_c] with y_c[x] = (v_c[x] + v_{3+c}[x + e_c]) / sqrt2
+      const T v1 = ax * zb[(size_t)c * g.N + x];
+      const T v2 = ax * zb[(size_t)(c + 3) * g.N + x];
+      const T v2p = ab[nb.p[c]] * zb[(size_t)(c + 3) * g.N + nb.p[c]];
+      const T v1m = ab[nb.m[c]] * zb[(size_t)c * g.N + nb.m[c]];
+      acc += (v1 + v2p) - (v1m + v2);
+    }
+    rb[x] = acc * T(0.70710678118654752440);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_cert_sigma(Geo g, const T* __restrict__ kap, const T* __restrict__ z0, const T* __restrict__ z1,
+             const T* __restrict__ a0, const T* __restrict__ a1, const double* __restrict__ phic,
+             double* __restrict__ out, const Prob* __restrict__ prob) {
+  const int b = blockIdx.y;
+  const Prob& P = prob[b];
+  const int par = P.k & 1;
+  const T* zb = (par ? z1 : z0) + (size_t)b * 6 * g.N;
+  const T* ab = (par ? a1 : a0) + (size_t)b * g.N;
+  const T* gam = kap + (size_t)P.field * g.N;
+  const double* pb = phic + (size_t)b * g.N;
+  const double s = 0.70710678118654752440;
+  double mx = 0.0, bad = 0.0, ynorm = 0.0;
+  for (uint32_t x = blockIdx.x * kThreads + threadIdx.x; x < g.N; x += gridDim.x * kThreads) {
+    const Nbr nb = neighbours(g, x);
+    const double ax = (double)ab[x];
+    double n2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // face c of x (y_df_c[x]) and face c of x - e_c (y_df_c[x - e_c])
+      const double yx = s * (ax * (double)zb[(size_t)c * g.N + x] +
+                             (double)ab[nb.p[c]] * (double)zb[(size_t)(c + 3) * g.N + nb.p[c]]);
+      const double ym = s * ((double)ab[nb.m[c]] * (double)zb[(size_t)c * g.N + nb.m[c]] +
+                             ax * (double)zb[(size_t)(c + 3) * g.N + x]);
+      const double fx = yx - (pb[nb.p[c]] - pb[x]);
+      const double fm = ym - (pb[x] - pb[nb.m[c]]);
+      n2 += 0.5 * (fx * fx + fm * fm);
+    }
+    const double nrm = sqrt(n2);
+    const double gm = (double)gam[x];
+    if (gm > 0.0) {
+      mx = fmax(mx, nrm / gm);
+    } else {
+      bad = fmax(bad, nrm);
+    }
+    ynorm = fmax(ynorm, nrm);
+  }
+  __shared__ double red[3][kThreads];
+  red[0][threadIdx.x] = mx;
+  red[1][threadIdx.x] = bad;
+  red[2][threadIdx.x] = ynorm;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) out[((size_t)b * gridDim.x + blockIdx.x) * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
 __global__ void __launch_bounds__(kThreads)
 k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n16) {
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n16; i += (size_t)gridDim.x * kThreads)

@@ -43,12 +43,35 @@ def _periodic_sq_dist_axis(centres: np.ndarray, c: float, n: int) -> np.ndarray:
 
 
 def _ball_mask(dims, centre, radius) -> np.ndarray:
-    """Voxels whose centre lies within `radius` of `centre` (periodic)."""
+    """Voxels whose centre lies within `radius` of `centre` (periodic), full grid."""
     n1, n2, n3 = dims
     d1 = _periodic_sq_dist_axis(voxel_centres(n1), centre[0], n1)
     d2 = _periodic_sq_dist_axis(voxel_centres(n2), centre[1], n2)
     d3 = _periodic_sq_dist_axis(voxel_centres(n3), centre[2], n3)
     return (d1[:, None, None] + d2[None, :, None] + d3[None, None, :]) <= radius * radius
+
+
+def _mark_ball(mask: np.ndarray, centre, radius) -> int:
+    """Set `mask` on the voxels of the periodic ball (centre, radius); visits only the
+    ball's bounding box.  Same voxel set as _ball_mask.  Returns the number of
+    voxels newly set."""
+    idx = []
+    for c, n in zip(centre, mask.shape):
+        lo = int(np.floor(c - radius - 0.5))
+        hi = int(np.ceil(c + radius - 0.5))
+        ii = np.arange(lo, hi + 1)
+        if ii.size >= n:
+            ii = np.arange(n)
+        ii = np.unique(ii % n)
+        d = np.abs(ii + 0.5 - c)
+        d = np.minimum(d, n - d)
+        idx.append((ii, d * d))
+    (i1, q1), (i2, q2), (i3, q3) = idx
+    inside = (q1[:, None, None] + q2[None, :, None] + q3[None, None, :]) <= radius * radius
+    sub = mask[np.ix_(i1, i2, i3)]
+    added = int(np.count_nonzero(inside & ~sub))
+    mask[np.ix_(i1, i2, i3)] = sub | inside
+    return added
 
 
 def boolean_spheres(dims, radius, target_fraction, kappa_incl, kappa_matrix, seed):
@@ -57,9 +80,10 @@ def boolean_spheres(dims, radius, target_fraction, kappa_incl, kappa_matrix, see
     rng = np.random.default_rng(seed)
     dims = tuple(int(d) for d in dims)
     incl = np.zeros(dims, dtype=bool)
-    while incl.mean() < target_fraction:
+    count, total = 0, incl.size
+    while count < target_fraction * total:
         c = rng.uniform(0.0, 1.0, 3) * np.array(dims, dtype=np.float64)
-        incl |= _ball_mask(dims, c, radius)
+        count += _mark_ball(incl, c, radius)
     return np.where(incl, kappa_incl, kappa_matrix).astype(np.float64)
 
 
@@ -103,10 +127,11 @@ def rsa_polydisperse_spheres(n, rmin, rmax, target_fraction, kappa_incl, kappa_m
     dims = (n, n, n)
     box = np.array(dims, dtype=np.float64)
     incl = np.zeros(dims, dtype=bool)
-    centres = np.empty((0, 3))
-    radii = np.empty((0,))
+    centres = np.zeros((0, 3))
+    radii = np.zeros((0,))
+    count, total = 0, incl.size
     attempts = 0
-    while incl.mean() < target_fraction:
+    while count < target_fraction * total:
         attempts += 1
         if attempts > 10_000_000:
             raise RuntimeError("RSA did not reach the target fraction")
@@ -116,7 +141,7 @@ def rsa_polydisperse_spheres(n, rmin, rmax, target_fraction, kappa_incl, kappa_m
             continue
         centres = np.vstack([centres, c])
         radii = np.append(radii, r)
-        incl |= _ball_mask(dims, c, r)
+        count += _mark_ball(incl, c, r)
     return np.where(incl, kappa_incl, kappa_matrix).astype(np.float64)
 
 

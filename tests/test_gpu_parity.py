@@ -170,6 +170,27 @@ def test_graph_replay_equals_eager_launches(dtype):
         assert torch.equal(a.phi, b.phi)
 
 
+def test_certificate_matches_oracle_and_brackets():
+    banner("certificate")
+    g = M.boolean_spheres((16, 12, 10), 3.0, 0.2, 5.0, 1.0, seed=13)
+    xb = (0.48, 0.6, 0.64)
+    # fixed iterations: the GPU certificate equals the oracle's for the same iterate
+    p = plan_of(g)
+    res = p.solve([xb], tol=1e-300, max_iter=25)
+    cert, sig = p.certificate()
+    ora = O.admm_solve(g, xb, tol=1e-300, max_iter=25)
+    ocert, osig = O.dual_certificate(g, xb, ora.v)
+    assert abs(sig[0, 0] - osig) <= 1e-9 * osig
+    assert abs(cert[0, 0] - ocert) <= 1e-9 * abs(ocert)
+    # converged: cert <= geff with a small gap, in both precisions
+    for dtype, gap in [(torch.float64, 1e-5), (torch.float32, 1e-4)]:
+        p = plan_of(g, dtype)
+        res = p.solve([xb, (1, 0, 0)], tol=1e-7 if dtype == torch.float64 else 1e-6, max_iter=40000)
+        cert, sig = p.certificate()
+        assert np.all(cert <= res.geff * (1 + 1e-6))
+        assert np.all(res.geff - cert <= gap * res.geff)
+
+
 def test_gradient_fp64_matches_oracle_and_fd():
     banner("gradient fp64")
     rng = np.random.default_rng(3)
