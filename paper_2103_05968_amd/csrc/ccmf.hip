@@ -116,6 +116,7 @@ struct ccmf_plan_s {
   // autotuned tile widths (complex lines per block) of the five Hartley passes
   // (0 forward k, 1 forward j, 2 fused i, 3 inverse j, 4 inverse k); 0 = rule of thumb
   int nlc_hint[5] = {0, 0, 0, 0, 0};
+  int var_hint[5] = {0, 0, 0, 0, 0};   // plan variant (ccmf_fft_pow2.h) per pass
   int64_t tuned_B = 0;
 
   // captured chunk of iterations (HIP graph), valid for the current state buffers
@@ -228,11 +229,11 @@ bool is_pow2_len(int n) { return n >= 2 && n <= 2048 && (n & (n - 1)) == 0; }
 
 // Launch the power-of-two Hartley kernel: NLC complex lines (2 NLC real lines) per
 // block, NLC * TPL <= 512 threads, padded LDS tile within 64 KiB.
-template <typename TI, typename TO, typename TC, int N>
-int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
-              bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob, int kind) {
-  constexpr int E = pow2::Plan<N>::E, TPL = N / E;
-  constexpr int LP = line_pitch<N>();
+template <typename TI, typename TO, typename TC, int N, int V>
+int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
+               bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob, int kind) {
+  constexpr int E = pow2::Plan<N, V>::E, TPL = N / E;
+  constexpr int LP = line_pitch<N, V>();
   int nlc = 16;
   if (kind >= 0 && p->nlc_hint[kind] > 0) {
     nlc = p->nlc_hint[kind];
@@ -258,17 +259,26 @@ int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, i
   dim3 block((unsigned)(nlc * TPL));
   const pow2::CX<TC>* tw = reinterpret_cast<const pow2::CX<TC>*>(twp);
   if (middle) {
-    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, false, true>), grid, block, lds, p->stream, in, out, tw, A, s1,
+    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, false, true>), grid, block, lds, p->stream, in, out, tw, A, s1,
                        s2, s3, prob);
   } else if (contig) {
-    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, true, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
+    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, true, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
                        s2, s3, prob);
   } else {
-    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, false, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
+    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, false, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
                        s2, s3, prob);
   }
   HIP_LAUNCH_CHECK();
   return CCMF_OK;
+}
+
+template <typename TI, typename TO, typename TC, int N>
+int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
+              bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob, int kind) {
+  const int var = kind >= 0 ? p->var_hint[kind] : 0;
+  if (var == 1)
+    return launch_p2v<TI, TO, TC, N, 1>(p, in, out, count, A, outers, contig, middle, twp, s1, s2, s3, prob, kind);
+  return launch_p2v<TI, TO, TC, N, 0>(p, in, out, count, A, outers, contig, middle, twp, s1, s2, s3, prob, kind);
 }
 
 // Launch one Hartley pass along `axis` over `count` fields: load TI from `in`,
@@ -503,7 +513,7 @@ int run_iteration(ccmf_plan_s* p, int it, bool timed) {
 // grouped into blocks, never the arithmetic of a line, so results do not depend
 // on it.  Winners are cached per (grid, dtype, batch) for the process.
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int64_t>, std::array<int, 5>> g_tune_cache;
+std::map<std::tuple<int, int, int, int, int64_t>, std::array<int, 10>> g_tune_cache;
 
 template <typename T>
 int run_pass(ccmf_plan_s* p, int kind) {
@@ -525,7 +535,10 @@ int autotune(ccmf_plan_s* p) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      for (int k = 0; k < 5; ++k) p->nlc_hint[k] = it->second[k];
+      for (int k = 0; k < 5; ++k) {
+        p->nlc_hint[k] = it->second[k];
+        p->var_hint[k] = it->second[5 + k];
+      }
       p->tuned_B = p->B;
       return CCMF_OK;
     }
@@ -535,27 +548,33 @@ int autotune(ccmf_plan_s* p) {
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  std::array<int, 5> best{};
+  std::array<int, 10> best{};
   const bool present[5] = {p->n[2] > 1, p->n[1] > 1, true, p->n[1] > 1, p->n[2] > 1};
   for (int kind = 0; kind < 5; ++kind) {
     best[kind] = 0;
+    best[5 + kind] = 0;
     if (!present[kind] || !is_pow2_len(p->ax[kind == 2 ? 0 : (kind == 1 || kind == 3) ? 1 : 2].n)) continue;
     float best_ms = 1e30f;
-    for (int nlc = 1; nlc <= 16; nlc <<= 1) {
-      p->nlc_hint[kind] = nlc;
-      if (run_pass<T>(p, kind) != CCMF_OK) continue;  // infeasible width (LDS or threads)
-      hipEventRecord(e0, p->stream);
-      for (int rep = 0; rep < 3; ++rep) run_pass<T>(p, kind);
-      hipEventRecord(e1, p->stream);
-      if (hipEventSynchronize(e1) != hipSuccess) break;
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best_ms) {
-        best_ms = ms;
-        best[kind] = nlc;
+    for (int var = 0; var < 2; ++var) {
+      for (int nlc = 1; nlc <= 16; nlc <<= 1) {
+        p->nlc_hint[kind] = nlc;
+        p->var_hint[kind] = var;
+        if (run_pass<T>(p, kind) != CCMF_OK) continue;  // infeasible width (LDS or threads)
+        hipEventRecord(e0, p->stream);
+        for (int rep = 0; rep < 3; ++rep) run_pass<T>(p, kind);
+        hipEventRecord(e1, p->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best[kind] = nlc;
+          best[5 + kind] = var;
+        }
       }
     }
     p->nlc_hint[kind] = best[kind];
+    p->var_hint[kind] = best[5 + kind];
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

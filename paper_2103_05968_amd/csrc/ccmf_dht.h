@@ -274,62 +274,62 @@ k_hartley(const TI* in, TO* out, const C2<TC>* __restrict__ tw, DhtArgs A,
 // ---------------------------------------------------------------------------
 // LDS position of line element p: one padding slot every E elements, so the
 // stride-E accesses of a stage (thread t writing t*E + r) spread over the banks.
-template <int N>
+template <int N, int V>
 __device__ __forceinline__ int pidx(int p) {
-  return p + p / pow2::Plan<N>::E;
+  return p + p / pow2::Plan<N, V>::E;
 }
-template <int N>
+template <int N, int V>
 constexpr int line_pitch() {
-  return N + N / pow2::Plan<N>::E + 1;  // odd pitch: consecutive lines start on different banks
+  return N + N / pow2::Plan<N, V>::E + 1;  // odd pitch: consecutive lines start on different banks
 }
 
-template <typename TC, int N>
+template <typename TC, int N, int V>
 __device__ __forceinline__ void fft_line_p2(pow2::CX<TC>* line, int t, const pow2::CX<TC>* __restrict__ tw) {
-  using P = pow2::Plan<N>;
+  using P = pow2::Plan<N, V>;
   constexpr int E = P::E, TPL = N / E;
   pow2::CX<TC> v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = line[pidx<N>(t + TPL * e)];
+  for (int e = 0; e < E; ++e) v[e] = line[pidx<N, V>(t + TPL * e)];
   pow2::stage_compute<TC, N, E, P::R0, 1>(v, t, tw);
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < E / P::R0; ++m)
 #pragma unroll
     for (int r = 0; r < P::R0; ++r)
-      line[pidx<N>(pow2::stage_out_pos<N, E, P::R0, 1>(t, m, r))] = v[m + r * (E / P::R0)];
+      line[pidx<N, V>(pow2::stage_out_pos<N, E, P::R0, 1>(t, m, r))] = v[m + r * (E / P::R0)];
   __syncthreads();
   if constexpr (P::R1 > 0) {
     constexpr int NS = P::R0;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = line[pidx<N>(t + TPL * e)];
+    for (int e = 0; e < E; ++e) v[e] = line[pidx<N, V>(t + TPL * e)];
     pow2::stage_compute<TC, N, E, P::R1, NS>(v, t, tw);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < E / P::R1; ++m)
 #pragma unroll
       for (int r = 0; r < P::R1; ++r)
-        line[pidx<N>(pow2::stage_out_pos<N, E, P::R1, NS>(t, m, r))] = v[m + r * (E / P::R1)];
+        line[pidx<N, V>(pow2::stage_out_pos<N, E, P::R1, NS>(t, m, r))] = v[m + r * (E / P::R1)];
     __syncthreads();
   }
   if constexpr (P::R2 > 0) {
     constexpr int NS = P::R0 * P::R1;
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = line[pidx<N>(t + TPL * e)];
+    for (int e = 0; e < E; ++e) v[e] = line[pidx<N, V>(t + TPL * e)];
     pow2::stage_compute<TC, N, E, P::R2, NS>(v, t, tw);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < E / P::R2; ++m)
 #pragma unroll
       for (int r = 0; r < P::R2; ++r)
-        line[pidx<N>(pow2::stage_out_pos<N, E, P::R2, NS>(t, m, r))] = v[m + r * (E / P::R2)];
+        line[pidx<N, V>(pow2::stage_out_pos<N, E, P::R2, NS>(t, m, r))] = v[m + r * (E / P::R2)];
     __syncthreads();
   }
 }
 
-template <typename TC, int N>
+template <typename TC, int N, int V>
 __device__ __forceinline__ TC hartley_p2(const pow2::CX<TC>* L, int lp, int line, int s) {
-  const pow2::CX<TC> zq = L[(line >> 1) * lp + pidx<N>(s)];
-  const pow2::CX<TC> zm = L[(line >> 1) * lp + pidx<N>((N - s) & (N - 1))];
+  const pow2::CX<TC> zq = L[(line >> 1) * lp + pidx<N, V>(s)];
+  const pow2::CX<TC> zm = L[(line >> 1) * lp + pidx<N, V>((N - s) & (N - 1))];
   if ((line & 1) == 0) return TC(0.5) * ((zq.x + zm.x) - (zq.y - zm.y));
   return TC(0.5) * ((zq.y + zm.y) + (zq.x - zm.x));
 }
@@ -350,7 +350,7 @@ struct alignas(sizeof(T) * V) VecT {
   T v[V];
 };
 
-template <typename TI, typename TO, typename TC, int N, bool CONTIG, bool MIDDLE>
+template <typename TI, typename TO, typename TC, int N, int V, bool CONTIG, bool MIDDLE>
 __global__ void __launch_bounds__(512)
 k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs A,
              const TC* __restrict__ s1, const TC* __restrict__ s2, const TC* __restrict__ s3,
@@ -358,8 +358,8 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
   extern __shared__ unsigned char smem_raw[];
   const int b = blockIdx.y;
   if (prob != nullptr && prob[b].done) return;
-  using P = pow2::Plan<N>;
-  constexpr int E = P::E, TPL = N / E, LP = line_pitch<N>();
+  using P = pow2::Plan<N, V>;
+  constexpr int E = P::E, TPL = N / E, LP = line_pitch<N, V>();
   const int nl = 1 << A.lognl;
   pow2::CX<TC>* L = reinterpret_cast<pow2::CX<TC>*>(smem_raw);
   TC* Lr = reinterpret_cast<TC*>(smem_raw);
@@ -383,17 +383,17 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
   if (A.vec) {
     if constexpr (CONTIG) {
       // rows: V consecutive samples of both rows of a pair per thread
-      constexpr int V = 16 / sizeof(TI);
-      constexpr int CH = N / V;
+      constexpr int VW = 16 / sizeof(TI);
+      constexpr int CH = N / VW;
       for (int e = threadIdx.x; e < (nl >> 1) * CH; e += blockDim.x) {
-        const int pr = e / CH, s0 = (e & (CH - 1)) * V;
-        VecT<TI, V> va, vb;
+        const int pr = e / CH, s0 = (e & (CH - 1)) * VW;
+        VecT<TI, VW> va, vb;
 #pragma unroll
-        for (int v = 0; v < V; ++v) va.v[v] = vb.v[v] = TI(0);
-        if (2 * pr < nvalid) va = *reinterpret_cast<const VecT<TI, V>*>(src + (size_t)(2 * pr) * A.ls + s0);
-        if (2 * pr + 1 < nvalid) vb = *reinterpret_cast<const VecT<TI, V>*>(src + (size_t)(2 * pr + 1) * A.ls + s0);
+        for (int v = 0; v < VW; ++v) va.v[v] = vb.v[v] = TI(0);
+        if (2 * pr < nvalid) va = *reinterpret_cast<const VecT<TI, VW>*>(src + (size_t)(2 * pr) * A.ls + s0);
+        if (2 * pr + 1 < nvalid) vb = *reinterpret_cast<const VecT<TI, VW>*>(src + (size_t)(2 * pr + 1) * A.ls + s0);
 #pragma unroll
-        for (int v = 0; v < V; ++v) L[pr * LP + pidx<N>(s0 + v)] = {TC(va.v[v]), TC(vb.v[v])};
+        for (int v = 0; v < VW; ++v) L[pr * LP + pidx<N, V>(s0 + v)] = {TC(va.v[v]), TC(vb.v[v])};
       }
     } else {
       // columns: both lines of a pair are adjacent in memory
@@ -403,7 +403,7 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
         VecT<TI, 2> v2;
         v2.v[0] = v2.v[1] = TI(0);
         if (2 * pr < nvalid) v2 = *reinterpret_cast<const VecT<TI, 2>*>(src + (size_t)sp * A.ss + 2 * pr);
-        L[pr * LP + pidx<N>(sp)] = {TC(v2.v[0]), TC(v2.v[1])};
+        L[pr * LP + pidx<N, V>(sp)] = {TC(v2.v[0]), TC(v2.v[1])};
       }
     }
   } else {
@@ -411,11 +411,11 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
       int s, l;
       tile_coords_p2<CONTIG, N>(e, A.lognl, s, l);
       const TC v = (l < nvalid) ? TC(src[(size_t)s * A.ss + (size_t)l * A.ls]) : TC(0);
-      Lr[((l >> 1) * LP + pidx<N>(s)) * 2 + (l & 1)] = v;
+      Lr[((l >> 1) * LP + pidx<N, V>(s)) * 2 + (l & 1)] = v;
     }
   }
   __syncthreads();
-  fft_line_p2<TC, N>(L + c * LP, t, twl);
+  fft_line_p2<TC, N, V>(L + c * LP, t, twl);
 
   if constexpr (MIDDLE) {
     // Scale the Hartley coefficients by m(q) = 1/(lambda(q) N) and repack them
@@ -428,7 +428,7 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
     pow2::CX<TC>* Lc = L + c * LP;
     for (int sp = t; sp <= N / 2; sp += TPL) {
       const int sm = (N - sp) & (N - 1);
-      const pow2::CX<TC> zs = Lc[pidx<N>(sp)], zm = Lc[pidx<N>(sm)];
+      const pow2::CX<TC> zs = Lc[pidx<N, V>(sp)], zm = Lc[pidx<N, V>(sm)];
       const TC ha_s = TC(0.5) * ((zs.x + zm.x) - (zs.y - zm.y));
       const TC hb_s = TC(0.5) * ((zs.y + zm.y) + (zs.x - zm.x));
       const TC ha_m = TC(0.5) * ((zm.x + zs.x) - (zm.y - zs.y));
@@ -437,27 +437,27 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
       const TC lam_a = s1v + sa, lam_b = s1v + sb;     // lambda(q) = -lam
       const TC ma = (sa >= TC(0) && lam_a > TC(0)) ? -TC(A.scale) / lam_a : TC(0);
       const TC mb = (sb >= TC(0) && lam_b > TC(0)) ? -TC(A.scale) / lam_b : TC(0);
-      Lc[pidx<N>(sp)] = {ha_s * ma, hb_s * mb};
-      Lc[pidx<N>(sm)] = {ha_m * ma, hb_m * mb};
+      Lc[pidx<N, V>(sp)] = {ha_s * ma, hb_s * mb};
+      Lc[pidx<N, V>(sm)] = {ha_m * ma, hb_m * mb};
     }
     __syncthreads();
-    fft_line_p2<TC, N>(L + c * LP, t, twl);
+    fft_line_p2<TC, N, V>(L + c * LP, t, twl);
   }
 
   if (A.vec) {
     if constexpr (CONTIG) {
-      constexpr int V = 16 / sizeof(TO);
-      constexpr int CH = N / V;
+      constexpr int VW = 16 / sizeof(TO);
+      constexpr int CH = N / VW;
       for (int e = threadIdx.x; e < (nl >> 1) * CH; e += blockDim.x) {
-        const int pr = e / CH, s0 = (e & (CH - 1)) * V;
-        VecT<TO, V> va, vb;
+        const int pr = e / CH, s0 = (e & (CH - 1)) * VW;
+        VecT<TO, VW> va, vb;
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          va.v[v] = TO(hartley_p2<TC, N>(L, LP, 2 * pr, s0 + v));
-          vb.v[v] = TO(hartley_p2<TC, N>(L, LP, 2 * pr + 1, s0 + v));
+        for (int v = 0; v < VW; ++v) {
+          va.v[v] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr, s0 + v));
+          vb.v[v] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr + 1, s0 + v));
         }
-        if (2 * pr < nvalid) *reinterpret_cast<VecT<TO, V>*>(dst + (size_t)(2 * pr) * A.ls + s0) = va;
-        if (2 * pr + 1 < nvalid) *reinterpret_cast<VecT<TO, V>*>(dst + (size_t)(2 * pr + 1) * A.ls + s0) = vb;
+        if (2 * pr < nvalid) *reinterpret_cast<VecT<TO, VW>*>(dst + (size_t)(2 * pr) * A.ls + s0) = va;
+        if (2 * pr + 1 < nvalid) *reinterpret_cast<VecT<TO, VW>*>(dst + (size_t)(2 * pr + 1) * A.ls + s0) = vb;
       }
     } else {
       const int lognlc = A.lognl - 1;
@@ -465,8 +465,8 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
         const int sp = e >> lognlc, pr = e & ((1 << lognlc) - 1);
         if (2 * pr < nvalid) {
           VecT<TO, 2> v2;
-          v2.v[0] = TO(hartley_p2<TC, N>(L, LP, 2 * pr, sp));
-          v2.v[1] = TO(hartley_p2<TC, N>(L, LP, 2 * pr + 1, sp));
+          v2.v[0] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr, sp));
+          v2.v[1] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr + 1, sp));
           *reinterpret_cast<VecT<TO, 2>*>(dst + (size_t)sp * A.ss + 2 * pr) = v2;
         }
       }
@@ -475,7 +475,7 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       int s, l;
       tile_coords_p2<CONTIG, N>(e, A.lognl, s, l);
-      if (l < nvalid) dst[(size_t)s * A.ss + (size_t)l * A.ls] = TO(hartley_p2<TC, N>(L, LP, l, s));
+      if (l < nvalid) dst[(size_t)s * A.ss + (size_t)l * A.ls] = TO(hartley_p2<TC, N, V>(L, LP, l, s));
     }
   }
 }

@@ -170,6 +170,23 @@ def test_graph_replay_equals_eager_launches(dtype):
         assert torch.equal(a.phi, b.phi)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_single_sphere_golden_full_size(dtype):
+    """Sec. 4.2 at the paper's size: 64^3, sphere of diameter 32, contrast 10, e_x,
+    tol 1e-4 -> geff = gamma_matrix (tests/golden/single_sphere_sec4_2.json)."""
+    import json
+    import os
+    banner(f"single sphere 64^3 {dtype}")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "single_sphere_sec4_2.json")))
+    g = M.single_sphere(gold["grid"][0], gold["sphere_diameter"], gold["gamma_sphere"], gold["gamma_matrix"])
+    p = plan_of(g, dtype)
+    r = p.solve([gold["load"]], tol=gold["tol"], max_iter=40000)
+    cert, _ = p.certificate()
+    assert r.converged
+    assert abs(r.geff[0, 0] - gold["geff"]) <= 1e-3 * gold["geff"]
+    assert cert[0, 0] <= gold["geff"] * (1 + 1e-6)
+
+
 def test_certificate_matches_oracle_and_brackets():
     banner("certificate")
     g = M.boolean_spheres((16, 12, 10), 3.0, 0.2, 5.0, 1.0, seed=13)
@@ -212,6 +229,36 @@ def test_gradient_fp64_matches_oracle_and_fd():
         fp = plan_of(gp).solve([xb], tol=1e-12, max_iter=200000).geff[0, 0]
         fm = plan_of(gm).solve([xb], tol=1e-12, max_iter=200000).geff[0, 0]
         assert abs((fp - fm) / (2 * h) - g[idx]) <= 2e-4 * g.max()
+
+
+def test_gradient_single_voxel_fd_lognormal_fp64():
+    """Central differences of geff at 20 voxels (10 uniform, 10 from the top decile
+    of |xi*|) of a log-normal field, FP64, scaled-down cell of the differentiation
+    workload; the FP32 gradient is compared with the FP64 one."""
+    banner("gradient fd lognormal")
+    k = M.gaussian_lognormal(8, 2.0, 0.5, seed=4)
+    xb = tuple(np.ones(3) / np.sqrt(3.0))
+    p = plan_of(k)
+    p.solve([xb], tol=1e-10, max_iter=100000)
+    g = p.grad_kappa([1.0])[0].cpu().numpy()
+    g32 = plan_of(k, torch.float32)
+    g32.solve([xb], tol=1e-6, max_iter=100000)
+    gr32 = g32.grad_kappa([1.0])[0].cpu().numpy()
+    assert np.abs(gr32 - g).max() <= 5e-3 * g.max()
+    rng = np.random.default_rng(40)
+    flat = np.argsort(g.ravel())
+    idx = list(rng.choice(k.size, 10, replace=False)) + list(rng.choice(flat[-k.size // 10:], 10, replace=False))
+    h = 1e-2
+    for n, q in enumerate(idx):
+        v = np.unravel_index(q, k.shape)
+        kp, km = k.copy(), k.copy()
+        kp[v] += h * k[v]
+        km[v] -= h * k[v]
+        fp = plan_of(kp).solve([xb], tol=1e-9, max_iter=100000).geff[0, 0]
+        fm = plan_of(km).solve([xb], tol=1e-9, max_iter=100000).geff[0, 0]
+        fd = (fp - fm) / (2 * h * k[v])
+        banner(f"  voxel {n} {v}: fd {fd:.6e} grad {g[v]:.6e}")
+        assert abs(fd - g[v]) <= 1e-2 * g.max(), (v, fd, g[v])
 
 
 def test_autograd_function():

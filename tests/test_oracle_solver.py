@@ -103,6 +103,19 @@ def test_bounds_and_planar_cut(rng):
     assert gamma.min() - 1e-9 <= r2.geff <= gamma.mean() + 1e-9
 
 
+def test_single_sphere_golden_fixture_scaled_down():
+    """The printed result of Sec. 4.2 (tests/golden/single_sphere_sec4_2.json) on a
+    cell scaled by 1/4 (16^3, diameter 8): geff = gamma_matrix."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "single_sphere_sec4_2.json")))
+    n = gold["grid"][0] // 4
+    gamma = M.single_sphere(n, gold["sphere_diameter"] / 4, gold["gamma_sphere"], gold["gamma_matrix"])
+    r = solve(gamma, gold["load"], tol=gold["tol"])
+    assert r.converged
+    assert abs(r.geff - gold["geff"]) <= 1e-3 * gold["geff"]
+
+
 def test_single_tough_sphere_gives_matrix_value():
     """A tough sphere (10x the matrix) is bypassed by a planar crack: geff equals
     the matrix value (Sec. 4.2).  Scaled-down cell (16^3, diameter 8)."""
