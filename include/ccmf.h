@@ -78,6 +78,13 @@ typedef struct {
                           forced to eager when time_kernels is set)                          */
   int32_t no_autotune; /* nonzero: skip the tile-width autotuner of the spectral passes (run
                           once per plan and batch size, cached per process) and use defaults */
+  int32_t warm_start;  /* nonzero: resume from the plan's state -- the stopping state of the
+                          previous solve (same n_loads) or the one loaded by ccmf_set_state --
+                          instead of the initial state; rho^k, rho^{k-1} and the iteration
+                          index carry over (rho0 still sets the penalty limits), while tol,
+                          delta, rule, max_iter and the loads are taken from this call.  The
+                          stopping iterate is stepped again, so a solve stopped by max_iter
+                          and resumed follows the uninterrupted sequence bit for bit. */
 } ccmf_options;
 
 /* Create a plan for n_fields crack-resistance fields of size dims[0] x dims[1] x
@@ -121,6 +128,34 @@ int ccmf_grad_kappa(ccmf_plan p, const double* dL_dgeff, void* dkappa_dev);
  * cert: host out [B]; -inf when a voxel with gamma = 0 carries flux.  sigma: host out
  * [B] (nullable).  Allocates scratch (N doubles per problem) for the duration of the call. */
 int ccmf_certificate(ccmf_plan p, double* cert, double* sigma);
+
+/* Mean face flux <A* v^k> (eq:CCMF_FFT_AOperator_adjoint) of every problem of the last
+ * solve at its stopping iterate.  geff is the support function of the set of mean
+ * fluxes of the admissible flows of the max-flow form eq:CCMF_FFT_problemA, so at the
+ * optimum this is the gradient of the 1-homogeneous extension of geff with respect to
+ * the load xibar (not stated in the paper; it follows from that max-flow form), and
+ * <xibar, mflux> -> geff.  mflux: host out, [B][3].  Errors: CCMF_ESTATE before a solve. */
+int ccmf_mean_flux(ccmf_plan p, double* mflux);
+
+/* Checkpoint of the ADMM state of eq:CCMF_FFT_ADMM for every problem: the multiplier
+ * v^k and e^k of the state the last solve stopped at (or the one set by ccmf_set_state),
+ * the penalty rho^k and the global iteration index k.
+ * v_dev, e_dev: device out, [B][6][N] of the plan's dtype (nullable); components 0..2
+ * are the first half (xi1 of the operator A, eq:CCMF_FFT_AOperator), 3..5 the second.
+ * rho: host out [B] (nullable).  k: host out [B] (nullable).
+ * Errors: CCMF_ESTATE when the plan holds no state. */
+int ccmf_get_state(ccmf_plan p, void* v_dev, void* e_dev, double* rho, int32_t* k);
+
+/* Load a state (v^k, e^k, rho^k, k) for n_loads loads per field, b = f * n_loads + l,
+ * for a following ccmf_solve with options.warm_start set and the same n_loads.
+ * v_dev, e_dev: device, [B][6][N] of the plan's dtype, read during the call only.
+ * At every voxel v and e must be non-negative multiples of one 6-vector (every ADMM
+ * iterate is: v = P_C(z) and e = (z - v)/rho are both multiples of z); the plan stores
+ * z = v + rho e and |v|/|z|.  rho: host [B], > 0.  k: host [B], >= 0 (enters the
+ * penalty safeguard).  Errors: CCMF_EINVAL for bad sizes, rho or k, and for a pair
+ * that is not of that form at some voxel (the plan then holds no state). */
+int ccmf_set_state(ccmf_plan p, int64_t n_loads, const void* v_dev, const void* e_dev, const double* rho,
+                   const int32_t* k);
 
 /* Average device duration (ms) of the fused update kernel over the launches timed
  * since the last call (options.time_kernels), the number of launches, and the

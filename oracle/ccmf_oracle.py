@@ -186,6 +186,14 @@ class AdmmResult:
     e: np.ndarray               # e^k at the stopping iterate
     rho: float                  # rho^k used in the stopping iterate
     history: list = field(default_factory=list)   # (k, residual, rho^k, energy) per iteration
+    k: int = 0                  # global iteration index of the stopping state
+
+    @property
+    def mean_flux(self) -> np.ndarray:
+        """<A* v^k>: geff is the support function of the mean fluxes of the admissible
+        flows (max-flow form eq:CCMF_FFT_problemA), so at the optimum this is the
+        gradient of its 1-homogeneous extension in the load xibar."""
+        return self.flux.reshape(3, -1).mean(axis=1)
 
 
 def rho_initial(gamma: np.ndarray) -> float:
@@ -239,7 +247,7 @@ def admm_step(e, v, rho, xibar, gamma, delta):
 
 
 def admm_solve(gamma, xibar, tol=1e-4, delta=0.25, rule=RHO_BB, rho0=None,
-               max_iter=20000, record=False) -> AdmmResult:
+               max_iter=20000, record=False, start=None) -> AdmmResult:
     """Solve the CCMF min-cut / max-flow pair by the damped ADMM of Sec. 3.2.
 
     Scheme (eq:CCMF_FFT_ADMM, damped form), with w^k = e^k - v^k/rho^k:
@@ -252,6 +260,10 @@ def admm_solve(gamma, xibar, tol=1e-4, delta=0.25, rule=RHO_BB, rho0=None,
     checked on the pair (e^k, xi^{k+1/2}) of the same iteration (READING 5).
     Penalty rules of Sec. 3.2: Barzilai-Borwein (default), Lorenz-Tran-Dinh,
     or constant rho^0; the Barzilai-Borwein safeguard is ``bb_penalty``'s.
+
+    ``start = (e, v, rho, k)`` resumes from the state (e^k, v^k) with penalty
+    rho^k at global iteration index k (a warm start); ``max_iter`` then counts
+    the steps of this call and ``iterations`` reports them.
     """
     gamma = np.asarray(gamma, dtype=np.float64)
     if gamma.ndim != 3:
@@ -275,12 +287,18 @@ def admm_solve(gamma, xibar, tol=1e-4, delta=0.25, rule=RHO_BB, rho0=None,
     if not (r0 > 0.0 and math.isfinite(r0)):
         raise ValueError("rho0 must be positive and finite")
     rho = r0
+    k = 0
+    if start is not None:
+        e = np.array(start[0], dtype=np.float64).reshape((6,) + dims)
+        v = np.array(start[1], dtype=np.float64).reshape((6,) + dims)
+        rho = float(start[2])
+        k = int(start[3])
     history = []
     # READING 7: if gamma vanishes identically, g = 0 on all of K and the first
     # xi-step is optimal; the criterion (right-hand side 0) is then taken as met.
     all_zero = not np.any(gamma > 0)
 
-    k = 0
+    steps = 0
     while True:
         xi_half, phi, e_new, v_new = admm_step(e, v, rho, xb, gamma, delta)
         d = e - xi_half
@@ -290,15 +308,15 @@ def admm_solve(gamma, xibar, tol=1e-4, delta=0.25, rule=RHO_BB, rho0=None,
         E = energy(xi_half, gamma)
         if record:
             history.append((k, res, rho, E))
-        last = (k + 1 >= max_iter)
+        last = (steps + 1 >= max_iter)
         done = res <= tol * mvn or all_zero
         if done or last:
             return AdmmResult(
-                geff=E, iterations=k + 1, converged=bool(done),
+                geff=E, iterations=steps + 1, converged=bool(done),
                 residual=res, mean_v_norm=mvn,
                 dual_est=inner(A_xibar(xb, dims), v),
                 phi=phi, flux=A_adj(v), xi_half=xi_half, v=v, e=e, rho=rho,
-                history=history)
+                history=history, k=k)
 
         rho_new = rho
         if rule == RHO_BB:
@@ -318,6 +336,7 @@ def admm_solve(gamma, xibar, tol=1e-4, delta=0.25, rule=RHO_BB, rho0=None,
 
         e, v, rho = e_new, v_new, rho_new
         k += 1
+        steps += 1
 
 
 # ---------------------------------------------------------------------------

@@ -19,8 +19,9 @@ CCMF_F64 = 0
 CCMF_F32 = 1
 RULES = {"bb": 0, "const": 1, "ltd": 2}
 
-EXPORTS = ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_certificate", "ccmf_kernel_times", "ccmf_laplace_pinv",
-           "ccmf_hartley_axis", "ccmf_stream_copy", "ccmf_destroy", "ccmf_last_error")
+EXPORTS = ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_certificate", "ccmf_mean_flux", "ccmf_get_state",
+           "ccmf_set_state", "ccmf_kernel_times", "ccmf_laplace_pinv", "ccmf_hartley_axis", "ccmf_stream_copy",
+           "ccmf_destroy", "ccmf_last_error")
 
 
 class Options(ctypes.Structure):
@@ -28,7 +29,7 @@ class Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("time_kernels", ctypes.c_int32), ("bb_min_corr", ctypes.c_double),
                 ("eta0", ctypes.c_double), ("k0", ctypes.c_double), ("eager", ctypes.c_int32),
-                ("no_autotune", ctypes.c_int32)]
+                ("no_autotune", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
 
 
 class CcmfError(RuntimeError):
@@ -55,14 +56,17 @@ def load():
     lib.ccmf_grad_kappa.argtypes = [vp, pd, vp]
     lib.ccmf_kernel_times.argtypes = [vp, pd, pi64, pd]
     lib.ccmf_certificate.argtypes = [vp, pd, pd]
+    lib.ccmf_mean_flux.argtypes = [vp, pd]
+    lib.ccmf_get_state.argtypes = [vp, vp, vp, pd, pi32]
+    lib.ccmf_set_state.argtypes = [vp, i64, vp, vp, pd, pi32]
     lib.ccmf_laplace_pinv.argtypes = [vp, vp, vp, i64]
     lib.ccmf_hartley_axis.argtypes = [vp, vp, i64, i32]
     lib.ccmf_stream_copy.argtypes = [vp, vp, i64, vp]
     lib.ccmf_destroy.argtypes = [vp]
     lib.ccmf_destroy.restype = None
     lib.ccmf_last_error.restype = ctypes.c_char_p
-    for name in ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_certificate", "ccmf_kernel_times",
-                 "ccmf_laplace_pinv",
+    for name in ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_certificate", "ccmf_mean_flux",
+                 "ccmf_get_state", "ccmf_set_state", "ccmf_kernel_times", "ccmf_laplace_pinv",
                  "ccmf_hartley_axis", "ccmf_stream_copy"):
         getattr(lib, name).restype = i32
     _lib = lib

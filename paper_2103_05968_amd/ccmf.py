@@ -28,6 +28,7 @@ class SolveResult:
     residual: np.ndarray        # [F, L] |e^k - xi^{k+1/2}|_{L2} at the stopping iterate
     dual_est: np.ndarray        # [F, L] <A xibar, v^k>
     converged: bool
+    mean_flux: np.ndarray = None          # [F, L, 3] <A* v^k>: d geff / d xibar at the optimum
     phi: Optional[torch.Tensor] = None    # [F, L, N1, N2, N3], float64
     flux: Optional[torch.Tensor] = None   # [F, L, 3, N1, N2, N3]
 
@@ -87,14 +88,15 @@ class Plan:
               rule: str = "bb", rho0: float = 0.0, max_iter: int = 20000, check_every: int = 32,
               want_phi: bool = False, want_flux: bool = False, time_kernels: bool = False,
               raise_not_converged: bool = False, bb_min_corr: float = 0.0, eta0: float = 0.0,
-              k0: float = 0.0, eager: bool = False, autotune: bool = True) -> SolveResult:
+              k0: float = 0.0, eager: bool = False, autotune: bool = True,
+              warm_start: bool = False) -> SolveResult:
         xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(-1, 3))
         L = xi.shape[0]
         B = self.n_fields * L
         opt = _lib.Options(delta=delta, rho0=rho0, rule=_lib.RULES[rule], max_iter=max_iter,
                            check_every=check_every, time_kernels=int(bool(time_kernels)),
                            bb_min_corr=bb_min_corr, eta0=eta0, k0=k0, eager=int(bool(eager)),
-                           no_autotune=int(not autotune))
+                           no_autotune=int(not autotune), warm_start=int(bool(warm_start)))
         geff = np.zeros(B)
         iters = np.zeros(B, dtype=np.int32)
         res = np.zeros(B)
@@ -114,8 +116,41 @@ class Plan:
         _lib.check(code, allow_not_converged=not raise_not_converged)
         self.n_loads = L
         shape = (self.n_fields, L)
+        mflux = np.zeros((B, 3))
+        _lib.check(self._lib.ccmf_mean_flux(self._h, mflux.ctypes.data_as(dp)))
         return SolveResult(geff.reshape(shape), iters.reshape(shape), res.reshape(shape),
-                           dual.reshape(shape), code == _lib.CCMF_OK, phi, flux)
+                           dual.reshape(shape), code == _lib.CCMF_OK, mflux.reshape(shape + (3,)), phi, flux)
+
+    def get_state(self):
+        """(v, e, rho, k) of the plan's state: v, e [F, L, 6, N1, N2, N3] in the plan's dtype."""
+        B = self.n_fields * self.n_loads
+        if B == 0:   # no solve yet: the library reports the missing state
+            _lib.check(self._lib.ccmf_get_state(self._h, None, None, None, None))
+        v = torch.empty((self.n_fields, self.n_loads, 6) + self.dims, dtype=self.dtype, device=self.device)
+        e = torch.empty_like(v)
+        rho = np.zeros(B)
+        k = np.zeros(B, dtype=np.int32)
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.ccmf_get_state(self._h, _dptr(v), _dptr(e),
+                                                rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return v, e, rho.reshape(self.n_fields, -1), k.reshape(self.n_fields, -1)
+
+    def set_state(self, v: torch.Tensor, e: torch.Tensor, rho, k):
+        """Load (v, e, rho, k), v and e [F, L, 6, N1, N2, N3], for solve(..., warm_start=True)."""
+        L = v.numel() // (self.n_fields * 6 * self.N)
+        if v.shape != e.shape or v.numel() != self.n_fields * L * 6 * self.N or L < 1:
+            raise ValueError("v and e must have shape [F, L, 6, N1, N2, N3]")
+        v = v.to(self.dtype).contiguous()
+        e = e.to(self.dtype).contiguous()
+        B = self.n_fields * L
+        rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, dtype=np.float64).reshape(-1), (B,)))
+        k = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32).reshape(-1), (B,)))
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.ccmf_set_state(self._h, L, _dptr(v), _dptr(e),
+                                                rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        self.n_loads = L
 
     def grad_kappa(self, dL_dgeff) -> torch.Tensor:
         """Envelope gradient of the last solve: sum_l dL/dgeff[f,l] * |xi*_{f,l}[x]|/N."""
@@ -172,23 +207,41 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor, stream: Optional[torch.cud
 
 
 class GeffFunction(torch.autograd.Function):
-    """geff(kappa) for fixed loads, differentiable in kappa by the envelope theorem."""
+    """geff(kappa; xi) differentiable in kappa (envelope theorem on the min-cut form) and
+    in the loads xi [L, 3]: the value is geff of the unit direction xi/|xi|, whose gradient
+    is (m - geff xi/|xi|)/|xi| with m the mean face flux (the gradient of the 1-homogeneous
+    extension)."""
 
     @staticmethod
     def forward(ctx, kappa, xi, tol, solve_kwargs):
         plan = Plan(kappa.detach())
-        res = plan.solve(xi, tol, **(solve_kwargs or {}))
+        xin = np.asarray(xi.detach().cpu().double().numpy() if torch.is_tensor(xi) else xi,
+                         dtype=np.float64).reshape(-1, 3)
+        res = plan.solve(xin, tol, **(solve_kwargs or {}))
         ctx.plan = plan
         ctx.kappa_shape = kappa.shape
+        ctx.xi_tensor = torch.is_tensor(xi)
+        ctx.xi_meta = (xi.shape, xi.dtype, xi.device) if torch.is_tensor(xi) else None
+        ctx.xin = xin
+        ctx.geff = res.geff
+        ctx.mflux = res.mean_flux
         return torch.as_tensor(res.geff, dtype=torch.float64, device=kappa.device).reshape(
             (plan.n_fields, -1) if kappa.dim() == 4 else (-1,))
 
     @staticmethod
     def backward(ctx, grad_out):
         plan = ctx.plan
-        g = plan.grad_kappa(grad_out.detach().double().cpu().numpy())
+        go = grad_out.detach().double().cpu().numpy().reshape(plan.n_fields, -1)
+        g = plan.grad_kappa(go) if ctx.needs_input_grad[0] else None
         plan.close()
-        return g.reshape(ctx.kappa_shape), None, None, None
+        gxi = None
+        if ctx.xi_tensor and ctx.needs_input_grad[1]:
+            nr = np.linalg.norm(ctx.xin, axis=1)                       # [L]
+            u = ctx.xin / nr[:, None]
+            tang = (ctx.mflux - ctx.geff[..., None] * u[None]) / nr[None, :, None]   # [F, L, 3]
+            shape, dtype, device = ctx.xi_meta
+            gxi = torch.as_tensor((go[..., None] * tang).sum(0)).reshape(shape).to(device=device, dtype=dtype)
+        return (g.reshape(ctx.kappa_shape) if g is not None else None), gxi, None, None
 
 
 def effective_crack_energy(kappa: torch.Tensor, xi, tol: float = 1e-4, **solve_kwargs) -> torch.Tensor:

@@ -111,13 +111,17 @@ struct ccmf_plan_s {
   Prob* prob = nullptr;    // device
   Prob* probh = nullptr;   // pinned host
   bool solved = false;
+  bool state_ready = false;  // z[.]/a[.] and probh hold a state a warm start can resume
   int upd_blocks = 0, tiles_per_blk = 0, tpp = 0;
 
   // autotuned tile widths (complex lines per block) of the five Hartley passes
   // (0 forward k, 1 forward j, 2 fused i, 3 inverse j, 4 inverse k); 0 = rule of thumb
-  int nlc_hint[5] = {0, 0, 0, 0, 0};
-  int var_hint[5] = {0, 0, 0, 0, 0};   // plan variant (ccmf_fft_pow2.h) per pass
+  // kind 5: r = div^- A* w fused with the forward k pass
+  int nlc_hint[6] = {0, 0, 0, 0, 0, 0};
+  int var_hint[6] = {0, 0, 0, 0, 0, 0};   // plan variant (ccmf_fft_pow2.h) per pass
+  int planes_hint = 0;                    // planes walked per block by the fused kernel
   int64_t tuned_B = 0;
+  bool tuned_off = false;
 
   // captured chunk of iterations (HIP graph), valid for the current state buffers
   hipGraphExec_t gexec = nullptr;
@@ -186,7 +190,7 @@ Geo make_geo(const ccmf_plan_s* p) {
   g.n23 = p->n[1] * p->n[2];
   g.N = p->N;
   g.nloads = (int32_t)p->nloads;
-  g.tiles = (int32_t)((p->N + kThreads - 1) / kThreads);
+  g.tiles = (int32_t)((p->N + kUpd - 1) / kUpd);
   g.tiles_per_blk = p->tiles_per_blk;
   g.tpp = p->tpp;
   return g;
@@ -362,13 +366,70 @@ int launch_hartley(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, int axi
   return CCMF_OK;
 }
 
+// r = div^- A* w fused with the forward k pass (power-of-two n3 >= 4)
+bool fused_div_ok(const ccmf_plan_s* p) { return p->n[2] >= 4 && is_pow2_len(p->n[2]); }
+
+template <typename T, int N, int V>
+int launch_div_p2v(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, const Prob* prob) {
+  constexpr int E = pow2::Plan<N, V>::E, TPL = N / E;
+  constexpr int LP = line_pitch<N, V>();
+  int nlc = p->nlc_hint[5] > 0 ? p->nlc_hint[5] : 16;
+  if (p->nlc_hint[5] <= 0)
+    while (nlc > 1 && (nlc * TPL > 512 || (size_t)(nlc * LP + N) * 2 * sizeof(T) > 65536)) nlc >>= 1;
+  const size_t lds = (size_t)(nlc * LP + N) * 2 * sizeof(T);
+  if (lds > 65536 || nlc * TPL > 512) return fail(CCMF_EINVAL, "fused tile of %d lines does not fit", 2 * nlc);
+  DivArgs D;
+  D.n1 = p->n[0];
+  D.n2 = p->n[1];
+  D.n3 = p->n[2];
+  D.nl = 2 * nlc;
+  D.lognl = 0;
+  while ((1 << D.lognl) < D.nl) ++D.lognl;
+  D.jtiles = (D.n2 + D.nl - 1) / D.nl;
+  int planes = p->planes_hint;
+  if (planes <= 0) planes = std::max(1, (D.jtiles * D.n1) / 2048);
+  planes = std::min(planes, D.n1);
+  D.planes = planes;
+  D.ichunks = (D.n1 + planes - 1) / planes;
+  D.vec = ((reinterpret_cast<uintptr_t>(r) & 15) == 0 && N * (int)sizeof(T) >= 16) ? 1 : 0;
+  dim3 grid((unsigned)(D.jtiles * D.ichunks), (unsigned)count);
+  const pow2::CX<T>* tw = reinterpret_cast<const pow2::CX<T>*>(p->ax[2].tw[prec_index<T>()]);
+  hipLaunchKernelGGL((k_div_hartley_p2<T, N, V>), grid, dim3((unsigned)(nlc * TPL)), lds, p->stream, z, a, r, tw,
+                     D, prob);
+  HIP_LAUNCH_CHECK();
+  return CCMF_OK;
+}
+
+template <typename T, int N>
+int launch_div_p2(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, const Prob* prob) {
+  if (p->var_hint[5] == 1) return launch_div_p2v<T, N, 1>(p, z, a, r, count, prob);
+  return launch_div_p2v<T, N, 0>(p, z, a, r, count, prob);
+}
+
+template <typename T>
+int launch_div_fused(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, const Prob* prob) {
+  switch (p->n[2]) {
+    case 4: return launch_div_p2<T, 4>(p, z, a, r, count, prob);
+    case 8: return launch_div_p2<T, 8>(p, z, a, r, count, prob);
+    case 16: return launch_div_p2<T, 16>(p, z, a, r, count, prob);
+    case 32: return launch_div_p2<T, 32>(p, z, a, r, count, prob);
+    case 64: return launch_div_p2<T, 64>(p, z, a, r, count, prob);
+    case 128: return launch_div_p2<T, 128>(p, z, a, r, count, prob);
+    case 256: return launch_div_p2<T, 256>(p, z, a, r, count, prob);
+    case 512: return launch_div_p2<T, 512>(p, z, a, r, count, prob);
+    case 1024: return launch_div_p2<T, 1024>(p, z, a, r, count, prob);
+    case 2048: return launch_div_p2<T, 2048>(p, z, a, r, count, prob);
+    default: return fail(CCMF_EINVAL, "fused divergence needs a power-of-two n3");
+  }
+}
+
 // phi = (div^- grad^+)^dagger r: forward passes along k and j in place on r (the
 // plan dtype), the fused axis-i pass reads r and writes phi in FP64, the inverse
 // passes along j and k run in FP64 in place on phi.
 template <typename T>
-int launch_laplace(ccmf_plan_s* p, T* r, double* phi, int64_t count, const Prob* prob) {
+int launch_laplace(ccmf_plan_s* p, T* r, double* phi, int64_t count, const Prob* prob, bool k_done = false) {
   int rc;
-  if (p->n[2] > 1 && (rc = launch_hartley<T, T, T>(p, r, r, count, 2, false, prob, 0))) return rc;
+  if (!k_done && p->n[2] > 1 && (rc = launch_hartley<T, T, T>(p, r, r, count, 2, false, prob, 0))) return rc;
   if (p->n[1] > 1 && (rc = launch_hartley<T, T, T>(p, r, r, count, 1, false, prob, 1))) return rc;
   if ((rc = launch_hartley<T, double, double>(p, r, phi, count, 0, true, prob, 2))) return rc;
   if (p->n[1] > 1 && (rc = launch_hartley<double, double, double>(p, phi, phi, count, 1, false, prob, 3)))
@@ -414,11 +475,11 @@ int ensure_state(ccmf_plan_s* p, int64_t nloads) {
   // fused update: up to 2048 blocks per problem, independent of the batch size,
   // so the FP64 reduction order (and every result) is the same batched or alone.
   // With whole tiles per i-plane a block walks planes (see tile_of).
-  const int tiles = (int)((p->N + kThreads - 1) / kThreads);
+  const int tiles = (int)((p->N + kUpd - 1) / kUpd);
   const int64_t n23 = (int64_t)p->n[1] * p->n[2];
   p->tpp = 0;
-  if (n23 % kThreads == 0) {
-    const int tpp = (int)(n23 / kThreads);
+  if (n23 % kUpd == 0) {
+    const int tpp = (int)(n23 / kUpd);
     int want = std::min(tiles, 2048);
     int cpb = std::max(1, (want + tpp - 1) / tpp);          // i-chunks per problem
     cpb = std::min(cpb, p->n[0]);
@@ -491,17 +552,22 @@ int run_iteration(ccmf_plan_s* p, int it, bool timed) {
   T* r = reinterpret_cast<T*>(p->r);
   const T* kap = reinterpret_cast<const T*>(p->kap);
   dim3 grid((unsigned)p->upd_blocks, (unsigned)p->B);
-  hipLaunchKernelGGL((k_div<T>), grid, dim3(kThreads), 0, p->stream, g, z0, a0, r, p->prob);
-  HIP_LAUNCH_CHECK();
-  int rc = launch_laplace<T>(p, r, p->phi, p->B, p->prob);
-  if (rc) return rc;
+  int rc;
+  const bool fused = fused_div_ok(p);
+  if (fused) {
+    if ((rc = launch_div_fused<T>(p, z0, a0, r, p->B, p->prob))) return rc;
+  } else {
+    hipLaunchKernelGGL((k_div<T>), grid, dim3(kUpd), 0, p->stream, g, z0, a0, r, p->prob);
+    HIP_LAUNCH_CHECK();
+  }
+  if ((rc = launch_laplace<T>(p, r, p->phi, p->B, p->prob, fused))) return rc;
   hipEvent_t e0, e1;
   if (timed && (rc = record_event(p, &e0))) return rc;
-  hipLaunchKernelGGL((k_update<T>), grid, dim3(kThreads), 0, p->stream, g, kap, z0, a0, p->phi, z1, a1,
+  hipLaunchKernelGGL((k_update<T>), grid, dim3(kUpd), 0, p->stream, g, kap, z0, a0, p->phi, z1, a1,
                      p->partials, p->prob);
   HIP_LAUNCH_CHECK();
   if (timed && (rc = record_event(p, &e1))) return rc;
-  hipLaunchKernelGGL(k_finish, dim3((unsigned)p->B), dim3(kThreads), 0, p->stream, p->N, p->upd_blocks,
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)p->B), dim3(kFinishThreads), 0, p->stream, p->N, p->upd_blocks,
                      p->partials, p->prob, (double*)nullptr, 0);
   HIP_LAUNCH_CHECK();
   return CCMF_OK;
@@ -513,7 +579,7 @@ int run_iteration(ccmf_plan_s* p, int it, bool timed) {
 // grouped into blocks, never the arithmetic of a line, so results do not depend
 // on it.  Winners are cached per (grid, dtype, batch) for the process.
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int64_t>, std::array<int, 10>> g_tune_cache;
+std::map<std::tuple<int, int, int, int, int64_t>, std::array<int, 13>> g_tune_cache;
 
 template <typename T>
 int run_pass(ccmf_plan_s* p, int kind) {
@@ -524,7 +590,10 @@ int run_pass(ccmf_plan_s* p, int kind) {
     case 1: return launch_hartley<T, T, T>(p, r, r, p->B, 1, false, nullptr, 1);
     case 2: return launch_hartley<T, double, double>(p, r, phi, p->B, 0, true, nullptr, 2);
     case 3: return launch_hartley<double, double, double>(p, phi, phi, p->B, 1, false, nullptr, 3);
-    default: return launch_hartley<double, double, double>(p, phi, phi, p->B, 2, false, nullptr, 4);
+    case 4: return launch_hartley<double, double, double>(p, phi, phi, p->B, 2, false, nullptr, 4);
+    default:
+      return launch_div_fused<T>(p, reinterpret_cast<const T*>(p->z[0]), reinterpret_cast<const T*>(p->a[0]), r,
+                                 p->B, p->prob);
   }
 }
 
@@ -535,10 +604,11 @@ int autotune(ccmf_plan_s* p) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      for (int k = 0; k < 5; ++k) {
+      for (int k = 0; k < 6; ++k) {
         p->nlc_hint[k] = it->second[k];
-        p->var_hint[k] = it->second[5 + k];
+        p->var_hint[k] = it->second[6 + k];
       }
+      p->planes_hint = it->second[12];
       p->tuned_B = p->B;
       return CCMF_OK;
     }
@@ -548,11 +618,12 @@ int autotune(ccmf_plan_s* p) {
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  std::array<int, 10> best{};
-  const bool present[5] = {p->n[2] > 1, p->n[1] > 1, true, p->n[1] > 1, p->n[2] > 1};
-  for (int kind = 0; kind < 5; ++kind) {
+  std::array<int, 13> best{};
+  const bool present[6] = {p->n[2] > 1, p->n[1] > 1, true, p->n[1] > 1, p->n[2] > 1, fused_div_ok(p)};
+  p->planes_hint = 0;
+  for (int kind = 0; kind < 6; ++kind) {
     best[kind] = 0;
-    best[5 + kind] = 0;
+    best[6 + kind] = 0;
     if (!present[kind] || !is_pow2_len(p->ax[kind == 2 ? 0 : (kind == 1 || kind == 3) ? 1 : 2].n)) continue;
     float best_ms = 1e30f;
     for (int var = 0; var < 2; ++var) {
@@ -569,12 +640,32 @@ int autotune(ccmf_plan_s* p) {
         if (ms < best_ms) {
           best_ms = ms;
           best[kind] = nlc;
-          best[5 + kind] = var;
+          best[6 + kind] = var;
         }
       }
     }
     p->nlc_hint[kind] = best[kind];
-    p->var_hint[kind] = best[5 + kind];
+    p->var_hint[kind] = best[6 + kind];
+  }
+  // planes walked per block by the fused divergence kernel
+  best[12] = 0;
+  if (present[5]) {
+    float best_ms = 1e30f;
+    for (int planes = 1; planes <= 8 && planes <= p->n[0]; planes <<= 1) {
+      p->planes_hint = planes;
+      if (run_pass<T>(p, 5) != CCMF_OK) continue;
+      hipEventRecord(e0, p->stream);
+      for (int rep = 0; rep < 3; ++rep) run_pass<T>(p, 5);
+      hipEventRecord(e1, p->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) break;
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best[12] = planes;
+      }
+    }
+    p->planes_hint = best[12];
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -617,21 +708,18 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
     if (!(nr > 0.0) || !std::isfinite(nr)) return fail(CCMF_EINVAL, "load %lld is zero or not finite", (long long)l);
   }
   if (p->nfields * nloads > 65535) return fail(CCMF_EINVAL, "at most 65535 problems per solve");
+  const bool warm = opt.warm_start != 0;
+  if (warm && !(p->state_ready && p->B == p->nfields * nloads))
+    return fail(CCMF_ESTATE, "warm start needs a preceding solve or ccmf_set_state with the same number of loads");
   int rc = ensure_state(p, nloads);
   if (rc) return rc;
   p->solved = false;
-  if (p->tuned_B != p->B) {
-    if (opt.no_autotune) {
-      for (int k = 0; k < 5; ++k) p->nlc_hint[k] = 0;
-      p->tuned_B = 0;
-    } else if ((rc = autotune<T>(p))) {
-      return rc;
-    }
-  }
+  p->state_ready = false;
 
   for (int64_t b = 0; b < p->B; ++b) {
     const int64_t f = b / nloads, l = b % nloads;
     Prob& P = p->probh[b];
+    const Prob kept = P;
     std::memset(&P, 0, sizeof(P));
     const double nr = std::sqrt(xi[3 * l] * xi[3 * l] + xi[3 * l + 1] * xi[3 * l + 1] + xi[3 * l + 2] * xi[3 * l + 2]);
     for (int c = 0; c < 3; ++c) P.xibar[c] = xi[3 * l + c] / nr;
@@ -650,15 +738,43 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
     P.max_iter = opt.max_iter;
     P.all_zero = any_pos ? 0 : 1;
     P.field = (int32_t)f;
+    if (warm) {
+      // resume the kept state k: penalties and iteration index carry over; the
+      // state moves to ping-pong slot 0, where the iteration sequence starts
+      P.rho = kept.rho;
+      P.rho_prev = kept.rho_prev;
+      P.k_off = kept.k_off + kept.k;
+      if (kept.k & 1) {
+        HIP_TRY(hipMemcpyAsync(static_cast<char*>(p->z[0]) + (size_t)b * 6 * p->N * p->esz,
+                               static_cast<const char*>(p->z[1]) + (size_t)b * 6 * p->N * p->esz,
+                               6 * p->N * p->esz, hipMemcpyDeviceToDevice, p->stream));
+        HIP_TRY(hipMemcpyAsync(static_cast<char*>(p->a[0]) + (size_t)b * p->N * p->esz,
+                               static_cast<const char*>(p->a[1]) + (size_t)b * p->N * p->esz,
+                               p->N * p->esz, hipMemcpyDeviceToDevice, p->stream));
+      }
+    }
   }
   HIP_TRY(hipMemcpyAsync(p->prob, p->probh, (size_t)p->B * sizeof(Prob), hipMemcpyHostToDevice, p->stream));
   const Geo g = make_geo(p);
-  {
+  if (!warm) {
     const int blocks = (int)std::min<uint64_t>(4096, (p->N + kThreads - 1) / kThreads);
     hipLaunchKernelGGL((k_init<T>), dim3(blocks, (unsigned)p->B), dim3(kThreads), 0, p->stream, g,
                        reinterpret_cast<const T*>(p->kap), reinterpret_cast<T*>(p->z[0]),
                        reinterpret_cast<T*>(p->a[0]), p->prob);
     HIP_LAUNCH_CHECK();
+  }
+  // tile widths of the spectral passes, timed on the initial state (results do
+  // not depend on them); the graph below is captured with the chosen widths
+  if (p->tuned_B != p->B || (opt.no_autotune != 0) != p->tuned_off) {
+    p->drop_graph();
+    if (opt.no_autotune) {
+      for (int k = 0; k < 6; ++k) p->nlc_hint[k] = p->var_hint[k] = 0;
+      p->planes_hint = 0;
+      p->tuned_B = p->B;
+    } else if ((rc = autotune<T>(p))) {
+      return rc;
+    }
+    p->tuned_off = opt.no_autotune != 0;
   }
   p->ev_used = 0;
   const bool eager = opt.eager != 0 || opt.time_kernels != 0;
@@ -729,6 +845,7 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
     if (dual_est) dual_est[b] = P.dual;
   }
   p->solved = true;
+  p->state_ready = true;
   if (phi_dev) {
     HIP_TRY(hipMemcpyAsync(phi_dev, p->phi, (size_t)p->B * p->N * sizeof(double), hipMemcpyDeviceToDevice,
                            p->stream));
@@ -915,6 +1032,87 @@ int ccmf_grad_kappa(ccmf_plan p, const double* dL_dgeff, void* dkappa_dev) {
 int ccmf_certificate(ccmf_plan p, double* cert, double* sigma) {
   if (!p) return fail(CCMF_EINVAL, "null plan");
   return p->dt == CCMF_F64 ? certificate_impl<double>(p, cert, sigma) : certificate_impl<float>(p, cert, sigma);
+}
+
+int ccmf_mean_flux(ccmf_plan p, double* mflux) {
+  if (!p || !mflux) return fail(CCMF_EINVAL, "null argument");
+  if (!p->solved) return fail(CCMF_ESTATE, "ccmf_mean_flux needs a preceding ccmf_solve");
+  for (int64_t b = 0; b < p->B; ++b)
+    for (int c = 0; c < 3; ++c) mflux[3 * b + c] = p->probh[b].mflux[c];
+  return CCMF_OK;
+}
+
+int ccmf_get_state(ccmf_plan p, void* v_dev, void* e_dev, double* rho, int32_t* k) {
+  if (!p) return fail(CCMF_EINVAL, "null plan");
+  if (!p->state_ready) return fail(CCMF_ESTATE, "ccmf_get_state needs a preceding ccmf_solve");
+  if (v_dev || e_dev) {
+    const Geo g = make_geo(p);
+    const int blocks = (int)std::min<uint64_t>(4096, (p->N + kThreads - 1) / kThreads);
+    if (p->dt == CCMF_F64) {
+      hipLaunchKernelGGL((k_get_state<double>), dim3(blocks, (unsigned)p->B), dim3(kThreads), 0, p->stream, g,
+                         static_cast<const double*>(p->z[0]), static_cast<const double*>(p->z[1]),
+                         static_cast<const double*>(p->a[0]), static_cast<const double*>(p->a[1]),
+                         static_cast<double*>(v_dev), static_cast<double*>(e_dev), p->prob);
+    } else {
+      hipLaunchKernelGGL((k_get_state<float>), dim3(blocks, (unsigned)p->B), dim3(kThreads), 0, p->stream, g,
+                         static_cast<const float*>(p->z[0]), static_cast<const float*>(p->z[1]),
+                         static_cast<const float*>(p->a[0]), static_cast<const float*>(p->a[1]),
+                         static_cast<float*>(v_dev), static_cast<float*>(e_dev), p->prob);
+    }
+    HIP_LAUNCH_CHECK();
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  for (int64_t b = 0; b < p->B; ++b) {
+    if (rho) rho[b] = p->probh[b].rho;
+    if (k) k[b] = p->probh[b].k_off + p->probh[b].k;
+  }
+  return CCMF_OK;
+}
+
+int ccmf_set_state(ccmf_plan p, int64_t n_loads, const void* v_dev, const void* e_dev, const double* rho,
+                   const int32_t* k) {
+  if (!p || !v_dev || !e_dev || !rho || !k) return fail(CCMF_EINVAL, "null argument");
+  if (n_loads < 1 || p->nfields * n_loads > 65535) return fail(CCMF_EINVAL, "n_loads out of range");
+  const int64_t B = p->nfields * n_loads;
+  for (int64_t b = 0; b < B; ++b) {
+    if (!(rho[b] > 0.0) || !std::isfinite(rho[b])) return fail(CCMF_EINVAL, "rho[%lld] must be positive", (long long)b);
+    if (k[b] < 0) return fail(CCMF_EINVAL, "k[%lld] must be >= 0", (long long)b);
+  }
+  int rc = ensure_state(p, n_loads);
+  if (rc) return rc;
+  p->solved = false;
+  p->state_ready = false;
+  for (int64_t b = 0; b < B; ++b) {
+    Prob& P = p->probh[b];
+    std::memset(&P, 0, sizeof(P));
+    P.rho = rho[b];
+    P.rho_prev = rho[b];
+    P.k_off = k[b];
+    P.field = (int32_t)(b / n_loads);
+  }
+  HIP_TRY(hipMemcpyAsync(p->prob, p->probh, (size_t)B * sizeof(Prob), hipMemcpyHostToDevice, p->stream));
+  const Geo g = make_geo(p);
+  const int blocks = p->upd_blocks;  // one count per block in the partials buffer
+  if (p->dt == CCMF_F64) {
+    hipLaunchKernelGGL((k_set_state<double>), dim3(blocks, (unsigned)B), dim3(kThreads), 0, p->stream, g,
+                       static_cast<const double*>(v_dev), static_cast<const double*>(e_dev),
+                       static_cast<double*>(p->z[0]), static_cast<double*>(p->a[0]), p->partials, p->prob);
+  } else {
+    hipLaunchKernelGGL((k_set_state<float>), dim3(blocks, (unsigned)B), dim3(kThreads), 0, p->stream, g,
+                       static_cast<const float*>(v_dev), static_cast<const float*>(e_dev),
+                       static_cast<float*>(p->z[0]), static_cast<float*>(p->a[0]), p->partials, p->prob);
+  }
+  HIP_LAUNCH_CHECK();
+  std::vector<double> cnt((size_t)B * blocks);
+  HIP_TRY(hipMemcpy2DAsync(cnt.data(), sizeof(double), p->partials, kNQ * sizeof(double), sizeof(double),
+                           (size_t)B * blocks, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  double bad = 0.0;
+  for (double c : cnt) bad += c;
+  if (bad > 0.0)
+    return fail(CCMF_EINVAL, "v and e are not non-negative multiples of one vector at %.0f voxels", bad);
+  p->state_ready = true;
+  return CCMF_OK;
 }
 
 int ccmf_kernel_times(ccmf_plan p, double* avg_ms, int64_t* count, double* bytes_per_launch) {

@@ -480,4 +480,108 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
   }
 }
 
+// ---------------------------------------------------------------------------
+// r = div^- A* w (the argument of the spectral solve, eq:CCMF_FFT_Gamma_2) fused
+// with the forward Hartley pass along k: a block forms r for nl whole k-rows of
+// one plane straight into its LDS tile, transforms them and writes the k-Hartley
+// coefficients, so r itself never goes through HBM.  Rows of a block are
+// consecutive j at fixed i; a block walks `planes` consecutive planes.  N = n3.
+// ---------------------------------------------------------------------------
+struct DivArgs {
+  int32_t n1, n2, n3;
+  int32_t nl, lognl;       // real lines (rows) per tile
+  int32_t jtiles;          // ceil(n2 / nl)
+  int32_t planes;          // planes walked per block
+  int32_t ichunks;         // ceil(n1 / planes)
+  int32_t vec;             // vector stores allowed
+};
+
+template <typename T, int N, int V>
+__global__ void __launch_bounds__(512)
+k_div_hartley_p2(const T* __restrict__ z, const T* __restrict__ a, T* __restrict__ rout,
+                 const pow2::CX<T>* __restrict__ tw, DivArgs D, const Prob* __restrict__ prob) {
+  extern __shared__ unsigned char smem_raw[];
+  const int b = blockIdx.y;
+  const Prob& P = prob[b];
+  if (P.done) return;
+  using PL = pow2::Plan<N, V>;
+  constexpr int E = PL::E, TPL = N / E, LP = line_pitch<N, V>();
+  const int nl = D.nl;
+  pow2::CX<T>* L = reinterpret_cast<pow2::CX<T>*>(smem_raw);
+  T* Lr = reinterpret_cast<T*>(smem_raw);
+  pow2::CX<T>* twl = L + (size_t)(nl >> 1) * LP;
+  for (int j = threadIdx.x; j < N; j += blockDim.x) twl[j] = tw[j];
+  const int c = threadIdx.x / TPL, t = threadIdx.x & (TPL - 1);
+
+  const T ir = T(1.0 / P.rho), irp = T(1.0 / P.rho_prev);
+  const uint32_t n23 = (uint32_t)D.n2 * N, NN = (uint32_t)D.n1 * n23;
+  const T* zb = z + (size_t)b * 6 * NN;
+  const T* ab = a + (size_t)b * NN;
+  T* rb = rout + (size_t)b * NN;
+
+  const int bx = xcd_remap(blockIdx.x, gridDim.x);
+  const int jt = bx % D.jtiles, ic = bx / D.jtiles;
+  const int j0 = jt * nl;
+  const int nvalid = min(nl, D.n2 - j0);
+  for (int step = 0; step < D.planes; ++step) {
+    const int i = ic * D.planes + step;
+    if (i >= D.n1) break;
+    const uint32_t ip = (i + 1 == D.n1) ? 0u : (uint32_t)(i + 1);
+    const uint32_t im = (i == 0) ? (uint32_t)(D.n1 - 1) : (uint32_t)(i - 1);
+    // r for the tile's rows, written into the LDS tile as real lines
+    for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
+      const int l = e / N, k = e & (N - 1);
+      T rv = T(0);
+      if (l < nvalid) {
+        const uint32_t j = (uint32_t)(j0 + l);
+        const uint32_t jp = (j + 1 == (uint32_t)D.n2) ? 0u : j + 1;
+        const uint32_t jm = (j == 0) ? (uint32_t)(D.n2 - 1) : j - 1;
+        const uint32_t kp = (k + 1 == N) ? 0u : (uint32_t)(k + 1);
+        const uint32_t km = (k == 0) ? (uint32_t)(N - 1) : (uint32_t)(k - 1);
+        const uint32_t row = (uint32_t)i * n23 + j * N;
+        const uint32_t x = row + k;
+        const uint32_t xp[3] = {ip * n23 + j * N + k, (uint32_t)i * n23 + jp * N + k, row + kp};
+        const uint32_t xm[3] = {im * n23 + j * N + k, (uint32_t)i * n23 + jm * N + k, row + km};
+        const T bx0 = beta_of(ab[x], irp, ir);
+        T acc = T(0);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const T w1 = bx0 * zb[(size_t)q * NN + x];
+          const T w2 = bx0 * zb[(size_t)(q + 3) * NN + x];
+          const T w2p = beta_of(ab[xp[q]], irp, ir) * zb[(size_t)(q + 3) * NN + xp[q]];
+          const T w1m = beta_of(ab[xm[q]], irp, ir) * zb[(size_t)q * NN + xm[q]];
+          acc += (w1 + w2p) - (w1m + w2);
+        }
+        rv = acc * T(0.70710678118654752440);
+      }
+      Lr[((l >> 1) * LP + pidx<N, V>(k)) * 2 + (l & 1)] = rv;
+    }
+    __syncthreads();
+    fft_line_p2<T, N, V>(L + c * LP, t, twl);
+    // k-Hartley coefficients of the tile's rows
+    T* dst = rb + (size_t)i * n23 + (size_t)j0 * N;
+    if (D.vec) {
+      constexpr int VW = 16 / sizeof(T);
+      constexpr int CH = N / VW;
+      for (int e = threadIdx.x; e < (nl >> 1) * CH; e += blockDim.x) {
+        const int pr = e / CH, s0 = (e & (CH - 1)) * VW;
+        VecT<T, VW> va, vb;
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+          va.v[v] = hartley_p2<T, N, V>(L, LP, 2 * pr, s0 + v);
+          vb.v[v] = hartley_p2<T, N, V>(L, LP, 2 * pr + 1, s0 + v);
+        }
+        if (2 * pr < nvalid) *reinterpret_cast<VecT<T, VW>*>(dst + (size_t)(2 * pr) * N + s0) = va;
+        if (2 * pr + 1 < nvalid) *reinterpret_cast<VecT<T, VW>*>(dst + (size_t)(2 * pr + 1) * N + s0) = vb;
+      }
+    } else {
+      for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
+        const int l = e / N, k = e & (N - 1);
+        if (l < nvalid) dst[(size_t)l * N + k] = hartley_p2<T, N, V>(L, LP, l, k);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace ccmf

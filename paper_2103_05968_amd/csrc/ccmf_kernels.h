@@ -19,6 +19,11 @@
 namespace ccmf {
 
 constexpr int kThreads = 256;
+#ifndef CCMF_UPD_THREADS
+#define CCMF_UPD_THREADS 256
+#endif
+// threads per block (= voxels per tile) of the stencil kernels k_div and k_update
+constexpr int kUpd = CCMF_UPD_THREADS;
 constexpr int kNQ = 16;  // FP64 partial sums per block (13 used)
 
 // indices of the per-block FP64 partial sums
@@ -44,7 +49,9 @@ struct Prob {
   double bb_corr, eta0, k0;
   double xibar[3];
   double geff, res, mvn, dual;
-  int32_t k;        // iteration index of the current state
+  double mflux[3];  // mean face flux <A* v^k> at the stopping iterate
+  int32_t k;        // iteration index of the current state within this solve
+  int32_t k_off;    // iterations before this solve (warm start); the global index is k_off + k
   int32_t done;     // 0 running, 1 converged, 2 stopped at max_iter
   int32_t rule, max_iter, all_zero, field;
 };
@@ -53,9 +60,9 @@ struct Geo {
   int32_t n1, n2, n3, n23;
   uint32_t N;
   int32_t nloads;
-  int32_t tiles;        // ceil(N / kThreads)
+  int32_t tiles;        // ceil(N / kUpd)
   int32_t tiles_per_blk;
-  int32_t tpp;          // tiles per i-plane when n2*n3 % kThreads == 0, else 0
+  int32_t tpp;          // tiles per i-plane when n2*n3 % kUpd == 0, else 0
 };
 
 // Tile visited by logical block lb at step m.  With whole tiles per plane, a
@@ -147,7 +154,7 @@ k_init(Geo g, const T* __restrict__ kap, T* __restrict__ z, T* __restrict__ a,
 // r[x] = (1/sqrt2) sum_c ( w1_c[x] + w2_c[x+e_c] - w1_c[x-e_c] - w2_c[x] ).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kUpd)
 k_div(Geo g, const T* __restrict__ z, const T* __restrict__ a, T* __restrict__ r,
       const Prob* __restrict__ prob) {
   const int b = blockIdx.y;
@@ -161,7 +168,7 @@ k_div(Geo g, const T* __restrict__ z, const T* __restrict__ a, T* __restrict__ r
   for (int m = 0; m < g.tiles_per_blk; ++m) {
     const int t = tile_of(g, lb, m);
     if (t >= g.tiles) break;
-    const uint32_t x = (uint32_t)t * kThreads + threadIdx.x;
+    const uint32_t x = (uint32_t)t * kUpd + threadIdx.x;
     if (x >= g.N) continue;
     const Nbr nb = neighbours(g, x);
     const T bx = beta_of(ab[x], irp, ir);
@@ -196,7 +203,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 //   z'        = v^k + rho^k xi^{k+1};  alpha' = min(1, gamma/|z'|)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kUpd)
 k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __restrict__ a,
          const double* __restrict__ phi, T* __restrict__ zn, T* __restrict__ an,
          double* __restrict__ partials, const Prob* __restrict__ prob) {
@@ -222,7 +229,7 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
   for (int m = 0; m < g.tiles_per_blk; ++m) {
     const int t = tile_of(g, lb, m);
     if (t >= g.tiles) break;
-    const uint32_t x = (uint32_t)t * kThreads + threadIdx.x;
+    const uint32_t x = (uint32_t)t * kUpd + threadIdx.x;
     if (x >= g.N) continue;
     const Nbr nb = neighbours(g, x);
     const T al = ab[x];
@@ -288,7 +295,7 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
   }
 
   // deterministic block reduction: wavefront shuffles, then fixed-order LDS sum
-  __shared__ double red[kThreads / 64][kNQU];
+  __shared__ double red[kUpd / 64][kNQU];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < kNQU; ++q) {
@@ -299,7 +306,7 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
   if (threadIdx.x < kNQU) {
     double sq = 0.0;
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) sq += red[w][threadIdx.x];
+    for (int w = 0; w < kUpd / 64; ++w) sq += red[w][threadIdx.x];
     partials[((size_t)b * gridDim.x + lb) * kNQ + threadIdx.x] = sq;
   }
 }
@@ -309,7 +316,9 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
 // eq:convergence_criterion and the adaptive penalty of Sec. 3.2 (device side, no
 // host round trip).  One block per problem.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads)
+constexpr int kFinishThreads = 1024;
+
+__global__ void __launch_bounds__(kFinishThreads)
 k_finish(uint32_t N, int nparts, const double* __restrict__ partials, Prob* __restrict__ prob,
          double* __restrict__ hist, int hist_len) {
   const int b = blockIdx.x;
@@ -318,24 +327,28 @@ k_finish(uint32_t N, int nparts, const double* __restrict__ partials, Prob* __re
   // the iteration index lives on the device, so a captured chunk of iterations
   // can be replayed unchanged
   const int it = P.k;
-  __shared__ double red[kThreads][kNQU];
+  // fixed-order reduction: per-thread rows in order, wavefront shuffle trees,
+  // then the waves in order
   double acc[kNQU];
 #pragma unroll
   for (int q = 0; q < kNQU; ++q) acc[q] = 0.0;
   const double* pp = partials + (size_t)b * nparts * kNQ;
-  for (int i = threadIdx.x; i < nparts; i += kThreads) {
+  for (int i = threadIdx.x; i < nparts; i += kFinishThreads) {
 #pragma unroll
     for (int q = 0; q < kNQU; ++q) acc[q] += pp[(size_t)i * kNQ + q];
   }
+  __shared__ double red[kFinishThreads / 64][kNQU];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < kNQU; ++q) red[threadIdx.x][q] = acc[q];
+  for (int q = 0; q < kNQU; ++q) {
+    const double sq = wave_sum<double>(acc[q]);
+    if (lane == 0) red[wv][q] = sq;
+  }
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kFinishThreads / 64; ++w)
 #pragma unroll
-      for (int q = 0; q < kNQU; ++q) red[threadIdx.x][q] += red[threadIdx.x + w][q];
-    }
-    __syncthreads();
+      for (int q = 0; q < kNQU; ++q) red[0][q] += red[w][q];
   }
   if (threadIdx.x != 0) return;
   const double invN = 1.0 / (double)N;
@@ -360,6 +373,9 @@ k_finish(uint32_t N, int nparts, const double* __restrict__ partials, Prob* __re
     P.res = res;
     P.mvn = mvn;
     P.dual = red[0][Q_DUAL] * invN;
+    // <A* v>_c = (<v1_c> + <v2_c>) / sqrt(2): the shift in A* leaves the mean unchanged
+    for (int c = 0; c < 3; ++c)
+      P.mflux[c] = (red[0][Q_MV + c] + red[0][Q_MV + 3 + c]) * invN * 0.70710678118654752440;
     P.done = conv ? 1 : 2;
     P.k = it;
     return;
@@ -376,7 +392,7 @@ k_finish(uint32_t N, int nparts, const double* __restrict__ partials, Prob* __re
   }
   double rn = P.rho;
   if (cand > 0.0 && isfinite(cand)) {
-    const double q = 1.0 + (double)it / P.k0;
+    const double q = 1.0 + (double)(it + P.k_off) / P.k0;
     const double grow = 1.0 + P.eta0 / (q * q);   // summable relative variation
     rn = fmin(fmax(cand, P.rho / grow), P.rho * grow);
     rn = fmin(fmax(rn, P.lo), P.hi);
@@ -408,6 +424,71 @@ k_flux(Geo g, const T* __restrict__ z0, const T* __restrict__ z1, const T* __res
       fb[(size_t)c * g.N + x] =
           s * (al * zb[(size_t)c * g.N + x] + ab[nb.p[c]] * zb[(size_t)(c + 3) * g.N + nb.p[c]]);
   }
+}
+
+// Checkpoint: v^k = alpha z and e^k = (1 - alpha) z / rho^{k-1} of the stopping state
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_get_state(Geo g, const T* __restrict__ z0, const T* __restrict__ z1, const T* __restrict__ a0,
+            const T* __restrict__ a1, T* __restrict__ v, T* __restrict__ e, const Prob* __restrict__ prob) {
+  const int b = blockIdx.y;
+  const Prob& P = prob[b];
+  const int par = P.k & 1;
+  const T* zb = (par ? z1 : z0) + (size_t)b * 6 * g.N;
+  const T* ab = (par ? a1 : a0) + (size_t)b * g.N;
+  const T irp = T(1.0 / P.rho_prev);
+  for (uint32_t x = blockIdx.x * kThreads + threadIdx.x; x < g.N; x += gridDim.x * kThreads) {
+    const T al = ab[x];
+    const T ce = (T(1) - al) * irp;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const T zq = zb[(size_t)q * g.N + x];
+      if (v) v[((size_t)b * 6 + q) * g.N + x] = al * zq;
+      if (e) e[((size_t)b * 6 + q) * g.N + x] = ce * zq;
+    }
+  }
+}
+
+// Warm start from a pair (v, e): with rho = rho^k (the plan sets rho^{k-1} = rho^k)
+// z = v + rho e and alpha = |v|/|z| reproduce v = alpha z and e = (1 - alpha) z / rho
+// exactly when v and e are non-negative multiples of one vector at every voxel, as
+// every ADMM iterate is.  Per block: number of voxels violating that (or not finite).
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_set_state(Geo g, const T* __restrict__ v, const T* __restrict__ e, T* __restrict__ z, T* __restrict__ a,
+            double* __restrict__ partials, const Prob* __restrict__ prob) {
+  const int b = blockIdx.y;
+  const double rho = prob[b].rho;
+  const T* vb = v + (size_t)b * 6 * g.N;
+  const T* eb = e + (size_t)b * 6 * g.N;
+  T* zb = z + (size_t)b * 6 * g.N;
+  T* ab = a + (size_t)b * g.N;
+  int bad = 0;
+  for (uint32_t x = blockIdx.x * kThreads + threadIdx.x; x < g.N; x += gridDim.x * kThreads) {
+    double vv = 0.0, ee = 0.0, ve = 0.0, zz = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double vq = (double)vb[(size_t)q * g.N + x], eq = (double)eb[(size_t)q * g.N + x];
+      const double zq = vq + rho * eq;
+      zb[(size_t)q * g.N + x] = T(zq);
+      vv += vq * vq;
+      ee += eq * eq;
+      ve += vq * eq;
+      zz += zq * zq;
+    }
+    const double nv = sqrt(vv), nz = sqrt(zz);
+    ab[x] = nz > 0.0 ? T(fmin(1.0, nv / nz)) : T(1);
+    const bool ok = isfinite(zz) && (nv * sqrt(ee) - ve <= 1e-6 * nv * sqrt(ee));
+    bad += ok ? 0 : 1;
+  }
+  __shared__ int cnt[kThreads];
+  cnt[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[((size_t)b * gridDim.x + blockIdx.x) * kNQ] = (double)cnt[0];
 }
 
 template <typename T>

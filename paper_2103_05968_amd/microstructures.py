@@ -27,6 +27,7 @@ import numpy as np
 
 __all__ = [
     "voxel_centres", "boolean_spheres", "rsa_discs_extruded", "rsa_polydisperse_spheres",
+    "hard_particle_packing", "packed_discs_extruded", "packed_spheres",
     "gaussian_lognormal", "boolean_cylinders", "single_sphere", "laminate",
     "config_c1", "config_c2", "config_c3", "config_c4", "config_c5", "CONFIGS",
 ]
@@ -117,6 +118,81 @@ def rsa_discs_extruded(n12, n3, radius, target_fraction, kappa_fibre, kappa_matr
         area |= (d1[:, None] + d2[None, :]) <= radius * radius
     kap2 = np.where(area, kappa_fibre, kappa_matrix).astype(np.float64)
     return np.repeat(kap2[:, :, None], n3, axis=2), centres
+
+
+def hard_particle_packing(ndim, count, box, fraction, seed, equilibrate=50, max_sweeps=50_000):
+    """Random non-overlapping packing of `count` equal discs (ndim 2) or spheres
+    (ndim 3) filling `fraction` of the periodic cube [0, box)^ndim, by Monte-Carlo
+    compression: random sequential addition at a radius giving 20 % fill, then
+    sweeps of random single-particle moves (rejected on overlap, step adapted to
+    ~40 % acceptance), after each of which the radius grows to half the smallest
+    centre distance, capped at the target; `equilibrate` further sweeps at the
+    target radius.  A stand-in for the mechanical-contraction packings of Sec. 4.3
+    and Sec. 4.5 (dense random packings of equal particles).
+    Returns (centres [count, ndim], radius)."""
+    rng = np.random.default_rng(seed)
+    unit = math.pi if ndim == 2 else 4.0 * math.pi / 3.0
+    big = (fraction * box ** ndim / (count * unit)) ** (1.0 / ndim)
+    r = big * min(1.0, (0.2 / fraction) ** (1.0 / ndim))
+
+    def sq_dists(x, c):
+        d = np.abs(x - c)
+        d = np.minimum(d, box - d)
+        return np.sum(d * d, axis=-1)
+
+    x = np.empty((0, ndim))
+    attempts = 0
+    while x.shape[0] < count:
+        attempts += 1
+        if attempts > 10_000_000:
+            raise RuntimeError("initial insertion failed")
+        c = rng.uniform(0.0, box, ndim)
+        if x.shape[0] and np.min(sq_dists(x, c)) < 4.0 * r * r:
+            continue
+        x = np.vstack([x, c])
+    step, settled = r, 0
+    for _ in range(max_sweeps):
+        accepted = 0
+        for i in rng.permutation(count):
+            t = (x[i] + rng.uniform(-step, step, ndim)) % box
+            q = sq_dists(x, t)
+            q[i] = np.inf
+            if q.min() >= 4.0 * r * r:
+                x[i] = t
+                accepted += 1
+        q = sq_dists(x[:, None, :], x[None, :, :])
+        np.fill_diagonal(q, np.inf)
+        r = min(big, 0.5 * math.sqrt(q.min()))
+        step = min(big, step * (1.2 if accepted > 0.4 * count else 0.8))
+        if r >= big:
+            settled += 1
+            if settled >= equilibrate:
+                return x, big
+    raise RuntimeError("packing did not reach the target fraction")
+
+
+def packed_discs_extruded(n12, n3, count, fraction, kappa_fibre, kappa_matrix, seed):
+    """Aligned fibres along e3: a dense random packing of `count` equal discs
+    (hard_particle_packing) in the e1-e2 plane, voxelised and extruded along e3
+    (the unidirectional composite of Sec. 4.3)."""
+    centres, radius = hard_particle_packing(2, count, float(n12), fraction, seed)
+    xc = voxel_centres(n12)
+    area = np.zeros((n12, n12), dtype=bool)
+    for c in centres:
+        area |= (_periodic_sq_dist_axis(xc, c[0], n12)[:, None]
+                 + _periodic_sq_dist_axis(xc, c[1], n12)[None, :]) <= radius * radius
+    kap2 = np.where(area, kappa_fibre, kappa_matrix).astype(np.float64)
+    return np.repeat(kap2[:, :, None], n3, axis=2)
+
+
+def packed_spheres(n, count, fraction, kappa_incl, kappa_matrix, seed):
+    """n^3 cell with a dense random packing of `count` equal spheres
+    (hard_particle_packing); kappa_incl = 0 gives the pores of Sec. 4.5."""
+    centres, radius = hard_particle_packing(3, count, float(n), fraction, seed)
+    incl = np.zeros((n, n, n), dtype=bool)
+    for c in centres:
+        _mark_ball(incl, c, radius)
+    return np.where(incl, kappa_incl, kappa_matrix).astype(np.float64)
 
 
 def rsa_polydisperse_spheres(n, rmin, rmax, target_fraction, kappa_incl, kappa_matrix, seed):

@@ -83,7 +83,7 @@ def fixed_k(gamma, xibar, K, dtype=torch.float64, rule="bb", delta=0.25):
     return res, ora
 
 
-@pytest.mark.parametrize("dims", [(16, 16, 16), (24, 20, 18), (15, 12, 10), (8, 1, 5)])
+@pytest.mark.parametrize("dims", [(16, 16, 16), (24, 20, 18), (15, 12, 10), (8, 1, 5), (12, 20, 16), (6, 40, 32)])
 @pytest.mark.parametrize("rule,delta", [("bb", 0.25), ("ltd", 0.25), ("const", 0.5)])
 def test_fixed_iterations_fp64_match_oracle(dims, rule, delta):
     banner(f"fixedK {dims} {rule} {delta}")

@@ -1,0 +1,179 @@
+"""GPU tests of the load gradient (mean face flux), the checkpoint of the ADMM
+state and the warm start, through the C ABI, against the FP64 oracle."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ccmf_oracle as O
+from paper_2103_05968_amd import microstructures as M
+
+from closed_forms import laminate_oblique_gradient
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def banner(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_05968_amd import ccmf  # noqa: F401  (fails loudly if the library is missing)
+
+
+def plan_of(kappa, dtype=torch.float64):
+    from paper_2103_05968_amd.ccmf import Plan
+    return Plan(torch.as_tensor(np.ascontiguousarray(kappa), dtype=dtype, device=DEV))
+
+
+def spheres(dims, seed=11):
+    return M.boolean_spheres(dims, 3.0, 0.2, 10.0, 1.0, seed=seed)
+
+
+XB = (0.48, 0.6, 0.64)
+
+
+# --- mean face flux = d geff / d xibar ---------------------------------------------
+
+@pytest.mark.parametrize("dims", [(24, 20, 18), (15, 12, 10)])
+def test_mean_flux_fixed_iterations_match_oracle(dims):
+    banner(f"mean flux fixedK {dims}")
+    g = spheres(dims)
+    res = plan_of(g).solve([XB], tol=1e-300, max_iter=30)
+    ora = O.admm_solve(g, XB, tol=1e-300, max_iter=30)
+    m = res.mean_flux[0, 0]
+    assert np.abs(m - ora.mean_flux).max() <= 1e-10 * np.abs(ora.mean_flux).max()
+    xb = np.asarray(XB) / np.linalg.norm(XB)
+    assert abs(xb @ m - res.dual_est[0, 0]) <= 1e-12 * abs(res.dual_est[0, 0])
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-6), (torch.float32, 2e-4)])
+def test_mean_flux_is_the_laminate_load_gradient(dtype, tol, rng):
+    banner(f"mean flux laminate {dtype}")
+    prof = rng.uniform(0.5, 3.0, 12)
+    gamma = M.laminate(prof, (12, 8, 8), axis=0)
+    loads = [(0.8, 0.6, 0.0), (-0.5, 0.5, 0.7071067811865476)]
+    res = plan_of(gamma, dtype).solve(loads, tol=1e-10 if dtype == torch.float64 else 1e-6, max_iter=200000)
+    for l, xb in enumerate(loads):
+        want = laminate_oblique_gradient(prof, xb)
+        assert np.abs(res.mean_flux[0, l] - want).max() <= tol * np.abs(want).max(), (l, res.mean_flux[0, l], want)
+
+
+def test_autograd_load_gradient():
+    banner("autograd xi")
+    from paper_2103_05968_amd.ccmf import effective_crack_energy
+    rng = np.random.default_rng(8)
+    g = rng.uniform(0.5, 2.0, (8, 6, 5))
+    k = torch.as_tensor(g, dtype=torch.float64, device=DEV)
+    xi = torch.tensor([[0.9, 0.3, -0.6], [0.0, 2.0, 0.5]], dtype=torch.float64, requires_grad=True)
+    ge = effective_crack_energy(k, xi, tol=1e-11, max_iter=200000)
+    (ge[0] + 2.0 * ge[1]).backward()
+    for l, w in enumerate((1.0, 2.0)):
+        x = xi.detach()[l].numpy()
+        nr = np.linalg.norm(x)
+        ora = O.admm_solve(g, x, tol=1e-11, max_iter=200000)
+        want = w * (ora.mean_flux - ora.geff * x / nr) / nr
+        assert np.abs(xi.grad[l].numpy() - want).max() <= 1e-6 * np.abs(ora.mean_flux).max(), l
+        # the value is 0-homogeneous in xi: no radial component
+        assert abs(float(xi.grad[l] @ xi.detach()[l])) <= 1e-7
+
+
+# --- warm start and checkpoint -------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("eager,k1", [(False, 17), (False, 18), (True, 18)])
+def test_resumed_solve_continues_the_uninterrupted_sequence(dtype, eager, k1):
+    # k1 = 18 stops in the odd ping-pong slot, which the warm start moves to slot 0
+    banner(f"warm start continuation {dtype} eager={eager} k1={k1}")
+    g = np.stack([spheres((16, 12, 10), 11), spheres((16, 12, 10), 12)])
+    loads = [(1, 0, 0), XB]
+    k2 = 25
+    whole = plan_of(g, dtype).solve(loads, tol=1e-300, max_iter=k1 + k2 - 1, eager=eager)
+    p = plan_of(g, dtype)
+    first = p.solve(loads, tol=1e-300, max_iter=k1, eager=eager)
+    _, _, _, kk = p.get_state()
+    assert np.all(kk == k1 - 1) and np.all(first.iterations == k1)
+    rest = p.solve(loads, tol=1e-300, max_iter=k2, eager=eager, warm_start=True)
+    assert np.all(rest.iterations == k2)
+    assert np.array_equal(rest.geff, whole.geff)
+    assert np.array_equal(rest.residual, whole.residual)
+    _, _, _, kk = p.get_state()
+    assert np.all(kk == k1 + k2 - 2)
+
+
+def test_get_state_matches_oracle():
+    banner("get_state vs oracle")
+    g = spheres((24, 20, 18))
+    p = plan_of(g)
+    p.solve([XB], tol=1e-300, max_iter=30)
+    ora = O.admm_solve(g, XB, tol=1e-300, max_iter=30)
+    v, e, rho, k = p.get_state()
+    assert k[0, 0] == ora.k == 29
+    assert abs(rho[0, 0] - ora.rho) <= 1e-12 * ora.rho
+    v = v[0, 0].cpu().numpy()
+    e = e[0, 0].cpu().numpy()
+    assert np.abs(v - ora.v).max() <= 1e-9 * np.abs(ora.v).max()
+    assert np.abs(e - ora.e).max() <= 1e-9 * np.abs(ora.e).max()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 2e-5)])
+def test_set_state_from_oracle_and_resume(dtype, tol):
+    banner(f"set_state from oracle {dtype}")
+    g = spheres((20, 16, 12), 3)
+    mid = O.admm_solve(g, XB, tol=1e-300, max_iter=20)
+    ora = O.admm_solve(g, XB, tol=1e-300, max_iter=15, start=(mid.e, mid.v, mid.rho, mid.k))
+    p = plan_of(g, dtype)
+    v = torch.as_tensor(mid.v[None, None], dtype=dtype, device=DEV)
+    e = torch.as_tensor(mid.e[None, None], dtype=dtype, device=DEV)
+    p.set_state(v, e, [mid.rho], [mid.k])
+    res = p.solve([XB], tol=1e-300, max_iter=15, warm_start=True)
+    assert res.iterations[0, 0] == 15
+    assert abs(res.geff[0, 0] - ora.geff) <= tol * ora.geff
+    assert np.abs(res.mean_flux[0, 0] - ora.mean_flux).max() <= tol * np.abs(ora.mean_flux).max()
+    _, _, rho, k = p.get_state()
+    assert k[0, 0] == ora.k
+    assert abs(rho[0, 0] - ora.rho) <= (1e-10 if dtype == torch.float64 else 1e-3) * ora.rho
+
+
+def test_state_round_trip_into_a_fresh_plan():
+    banner("state round trip")
+    g = spheres((16, 16, 16), 5)
+    a = plan_of(g)
+    a.solve([(1, 0, 0)], tol=1e-300, max_iter=40)
+    v, e, rho, k = a.get_state()
+    cont = a.solve([(1, 0, 0)], tol=1e-300, max_iter=10, warm_start=True)
+    b = plan_of(g)
+    b.set_state(v, e, rho, k)
+    res = b.solve([(1, 0, 0)], tol=1e-300, max_iter=10, warm_start=True)
+    assert abs(res.geff[0, 0] - cont.geff[0, 0]) <= 1e-12 * cont.geff[0, 0]
+
+
+def test_state_errors():
+    banner("state errors")
+    from paper_2103_05968_amd._lib import CcmfError
+    g = spheres((8, 8, 8), 2)
+    p = plan_of(g)
+    with pytest.raises(CcmfError, match="warm start"):
+        p.solve([(1, 0, 0)], tol=1e-6, warm_start=True)
+    with pytest.raises(CcmfError):
+        p.get_state()
+    rng = np.random.default_rng(0)
+    v = torch.as_tensor(rng.standard_normal((1, 1, 6, 8, 8, 8)), device=DEV)
+    e = torch.as_tensor(rng.standard_normal((1, 1, 6, 8, 8, 8)), device=DEV)
+    with pytest.raises(CcmfError, match="multiples"):
+        p.set_state(v, e, [1.0], [0])
+    with pytest.raises(CcmfError, match="warm start"):
+        p.solve([(1, 0, 0)], tol=1e-6, warm_start=True)
+    with pytest.raises(CcmfError, match="rho"):
+        p.set_state(v, e, [0.0], [0])
+    p.solve([(1, 0, 0), (0, 1, 0)], tol=1e-6)
+    with pytest.raises(CcmfError, match="warm start"):
+        p.solve([(1, 0, 0)], tol=1e-6, warm_start=True)

@@ -11,6 +11,7 @@ import scipy.optimize
 from oracle import ccmf_oracle as O
 from paper_2103_05968_amd import microstructures as M
 
+from closed_forms import laminate_oblique_gradient
 from dense_ops import dense_div_minus, dense_shift_back
 
 TIGHT = 1e-9
@@ -279,3 +280,52 @@ def test_envelope_gradient_matches_finite_differences(rng):
         fd = (solve(gp, xb, tol=1e-12, max_iter=200000).geff
               - solve(gm, xb, tol=1e-12, max_iter=200000).geff) / (2 * h)
         assert abs(fd - grad[idx]) < 2e-4 * max(grad.max(), 1e-3)
+
+
+# --- load gradient: mean face flux ------------------------------------------------
+
+@pytest.mark.parametrize("xibar", [(0.8, 0.6, 0.0), (-0.5, 0.5, 0.7071067811865476)])
+def test_mean_flux_is_the_laminate_load_gradient(rng, xibar):
+    prof = rng.uniform(0.5, 3.0, 6)
+    gamma = M.laminate(prof, (6, 2, 2), axis=0)
+    r = solve(gamma, xibar, tol=1e-11, max_iter=200000)
+    want = laminate_oblique_gradient(prof, xibar)
+    assert np.abs(r.mean_flux - want).max() < 1e-6 * np.abs(want).max()
+    # Euler's identity of the support function: <xibar, grad> = geff
+    xb = np.asarray(xibar, float) / np.linalg.norm(xibar)
+    assert abs(xb @ r.mean_flux - r.geff) < 1e-8 * r.geff
+
+
+def test_mean_flux_matches_load_finite_differences(rng):
+    gamma = rng.uniform(0.5, 2.5, (4, 3, 3))
+    xb = np.array([0.48, 0.6, 0.64])
+    r = solve(gamma, xb, tol=1e-12, max_iter=200000)
+    m = r.mean_flux
+    h = 1e-4
+    for t in (np.array([0.6, -0.48, 0.0]), np.array([0.0, 0.64, -0.6]) / 0.8772684879784524):
+        t = t - (t @ xb) * xb      # tangent to the unit sphere at xibar
+        fp = solve(gamma, xb + h * t, tol=1e-12, max_iter=200000).geff
+        fm = solve(gamma, xb - h * t, tol=1e-12, max_iter=200000).geff
+        # d/dh geff((xibar + h t)/|xibar + h t|) = <t, m> for t orthogonal to xibar
+        assert abs((fp - fm) / (2 * h) - t @ m) < 1e-6
+
+
+# --- warm start ------------------------------------------------------------------
+
+@pytest.mark.parametrize("rule", [O.RHO_BB, O.RHO_LTD])
+def test_resuming_a_stopped_solve_continues_the_same_sequence(rng, rule):
+    gamma = M.laminate(rng.uniform(0.5, 3.0, 5), (5, 4, 3), axis=0) * rng.uniform(0.8, 1.2, (5, 4, 3))
+    xb = (0.3, -0.5, 0.81)
+    k1, k2 = 17, 25
+    whole = O.admm_solve(gamma, xb, tol=1e-300, rule=rule, max_iter=k1 + k2 - 1)
+    first = O.admm_solve(gamma, xb, tol=1e-300, rule=rule, max_iter=k1)
+    assert first.k == k1 - 1 and first.iterations == k1
+    rest = O.admm_solve(gamma, xb, tol=1e-300, rule=rule, max_iter=k2,
+                        start=(first.e, first.v, first.rho, first.k))
+    assert rest.k == whole.k and rest.iterations == k2
+    assert rest.geff == whole.geff and rest.rho == whole.rho
+    assert np.array_equal(rest.v, whole.v) and np.array_equal(rest.e, whole.e)
+    # a converged state stays converged: resuming it stops after one step
+    conv = solve(gamma, xb, tol=1e-8, rule=rule)
+    again = O.admm_solve(gamma, xb, tol=1e-8, rule=rule, start=(conv.e, conv.v, conv.rho, conv.k))
+    assert again.iterations == 1 and again.geff == conv.geff
