@@ -34,7 +34,7 @@ HBM_PEAK_GBPS = 8000.0
 # Fabric traffic of the fused update kernel per launch and active problem on the 256^3 FP32
 # workload: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from the 2 GiB copy
 # kernel), see profiles/k_update_ud_fibres256_f32_traffic.md.  None once the kernel changes.
-K_UPDATE_TRAFFIC_C2 = (1045e6 + 472e6)
+K_UPDATE_TRAFFIC_C2 = None
 
 
 def log(msg):

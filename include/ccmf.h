@@ -67,15 +67,16 @@ typedef struct {
   int32_t check_every; /* host polls the device convergence flags every this many
                           iterations (the kernels stop by themselves); 0 selects 32          */
   int32_t time_kernels;/* nonzero: time every launch of the fused update kernel with HIP
-                          events on the plan's stream (read with ccmf_kernel_times)         */
+                          events on the plan's stream (read with ccmf_kernel_times); with
+                          graph replay the events are part of the graph and are read after
+                          each replay                                                      */
   double bb_min_corr;  /* Barzilai-Borwein estimate used only if <dv,de>/(|dv||de|) >= this,
                           else the Lorenz-Tran-Dinh value; 0 selects 0.2                    */
   double eta0;         /* safeguard: |log(rho_{k+1}/rho_k)| <= log(1 + eta0/(1+k/k0)^2), a
                           summable variation; 0 selects 1.0                                  */
   double k0;           /* see eta0; 0 selects 100                                             */
   int32_t eager;       /* nonzero: launch every kernel from the host; 0: capture one chunk of
-                          check_every iterations into a HIP graph once and replay it (also
-                          forced to eager when time_kernels is set)                          */
+                          check_every iterations into a HIP graph once and replay it         */
   int32_t no_autotune; /* nonzero: skip the tile-width autotuner of the spectral passes (run
                           once per plan and batch size, cached per process) and use defaults */
   int32_t warm_start;  /* nonzero: resume from the plan's state -- the stopping state of the

@@ -112,7 +112,8 @@ struct ccmf_plan_s {
   Prob* probh = nullptr;   // pinned host
   bool solved = false;
   bool state_ready = false;  // z[.]/a[.] and probh hold a state a warm start can resume
-  int upd_blocks = 0, tiles_per_blk = 0, tpp = 0;
+  int upd_blocks = 0;        // blocks per problem of the stencil kernels (k_div, k_update)
+  int tiles_per_blk = 0, tpp = 0;  // tile walk of the stencil kernels (see tile_of)
 
   // autotuned tile widths (complex lines per block) of the five Hartley passes
   // (0 forward k, 1 forward j, 2 fused i, 3 inverse j, 4 inverse k); 0 = rule of thumb
@@ -233,6 +234,22 @@ bool is_pow2_len(int n) { return n >= 2 && n <= 2048 && (n & (n - 1)) == 0; }
 
 // Launch the power-of-two Hartley kernel: NLC complex lines (2 NLC real lines) per
 // block, NLC * TPL <= 512 threads, padded LDS tile within 64 KiB.
+// gfx950 gives a workgroup up to 160 KiB of LDS; above 64 KiB the kernel has to
+// opt in (once per kernel).
+constexpr size_t kMaxLds = 163840;
+
+int allow_lds(const void* kernel, size_t lds) {
+  if (lds <= 65536) return CCMF_OK;
+  static std::mutex mu;
+  static std::vector<const void*> done;
+  std::lock_guard<std::mutex> lk(mu);
+  for (const void* k : done)
+    if (k == kernel) return CCMF_OK;
+  HIP_TRY(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds));
+  done.push_back(kernel);
+  return CCMF_OK;
+}
+
 template <typename TI, typename TO, typename TC, int N, int V>
 int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
                bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob, int kind) {
@@ -258,17 +275,21 @@ int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, 
     A.vec = (p->n[2] % 2 == 0) ? 1 : 0;
   if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) A.vec = 0;
   const size_t lds = (size_t)(nlc * LP + N) * 2 * sizeof(TC);
-  if (lds > 65536 || nlc * TPL > 512) return fail(CCMF_EINVAL, "transform length %d too large for the LDS tile", N);
+  if (lds > kMaxLds || nlc * TPL > 512) return fail(CCMF_EINVAL, "transform length %d too large for the LDS tile", N);
   dim3 grid((unsigned)(outers * A.tiles_per_outer), (unsigned)count);
   dim3 block((unsigned)(nlc * TPL));
   const pow2::CX<TC>* tw = reinterpret_cast<const pow2::CX<TC>*>(twp);
+  int rc;
   if (middle) {
+    if ((rc = allow_lds((const void*)k_hartley_p2<TI, TO, TC, N, V, false, true>, lds))) return rc;
     hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, false, true>), grid, block, lds, p->stream, in, out, tw, A, s1,
                        s2, s3, prob);
   } else if (contig) {
+    if ((rc = allow_lds((const void*)k_hartley_p2<TI, TO, TC, N, V, true, false>, lds))) return rc;
     hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, true, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
                        s2, s3, prob);
   } else {
+    if ((rc = allow_lds((const void*)k_hartley_p2<TI, TO, TC, N, V, false, false>, lds))) return rc;
     hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, false, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
                        s2, s3, prob);
   }
@@ -377,7 +398,9 @@ int launch_div_p2v(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, 
   if (p->nlc_hint[5] <= 0)
     while (nlc > 1 && (nlc * TPL > 512 || (size_t)(nlc * LP + N) * 2 * sizeof(T) > 65536)) nlc >>= 1;
   const size_t lds = (size_t)(nlc * LP + N) * 2 * sizeof(T);
-  if (lds > 65536 || nlc * TPL > 512) return fail(CCMF_EINVAL, "fused tile of %d lines does not fit", 2 * nlc);
+  if (lds > kMaxLds || nlc * TPL > 512) return fail(CCMF_EINVAL, "fused tile of %d lines does not fit", 2 * nlc);
+  int rc;
+  if ((rc = allow_lds((const void*)k_div_hartley_p2<T, N, V>, lds))) return rc;
   DivArgs D;
   D.n1 = p->n[0];
   D.n2 = p->n[1];
@@ -472,15 +495,16 @@ int kappa_stats(ccmf_plan_s* p) {
 int ensure_state(ccmf_plan_s* p, int64_t nloads) {
   const int64_t B = p->nfields * nloads;
   p->nloads = nloads;
-  // fused update: up to 2048 blocks per problem, independent of the batch size,
-  // so the FP64 reduction order (and every result) is the same batched or alone.
-  // With whole tiles per i-plane a block walks planes (see tile_of).
+  // stencil kernels: up to kUpdBlocks blocks per problem walking tiles (with
+  // whole tiles per i-plane a block walks planes, see tile_of); one FP64 partial
+  // row per block and problem.  The reduction order depends on the grid only, so
+  // every result is the same batched or alone.
   const int tiles = (int)((p->N + kUpd - 1) / kUpd);
   const int64_t n23 = (int64_t)p->n[1] * p->n[2];
   p->tpp = 0;
   if (n23 % kUpd == 0) {
     const int tpp = (int)(n23 / kUpd);
-    int want = std::min(tiles, 2048);
+    int want = std::min(tiles, kUpdBlocks);
     int cpb = std::max(1, (want + tpp - 1) / tpp);          // i-chunks per problem
     cpb = std::min(cpb, p->n[0]);
     p->tiles_per_blk = (p->n[0] + cpb - 1) / cpb;            // planes per block
@@ -488,7 +512,7 @@ int ensure_state(ccmf_plan_s* p, int64_t nloads) {
     p->upd_blocks = cpb * tpp;
     p->tpp = tpp;
   } else {
-    int want = std::min(tiles, 2048);
+    int want = std::min(tiles, kUpdBlocks);
     if (want > 8) want &= ~7;
     p->tiles_per_blk = (tiles + want - 1) / want;
     p->upd_blocks = (tiles + p->tiles_per_blk - 1) / p->tiles_per_blk;
@@ -551,19 +575,20 @@ int run_iteration(ccmf_plan_s* p, int it, bool timed) {
   T* a1 = reinterpret_cast<T*>(p->a[nxt]);
   T* r = reinterpret_cast<T*>(p->r);
   const T* kap = reinterpret_cast<const T*>(p->kap);
-  dim3 grid((unsigned)p->upd_blocks, (unsigned)p->B);
   int rc;
   const bool fused = fused_div_ok(p);
   if (fused) {
     if ((rc = launch_div_fused<T>(p, z0, a0, r, p->B, p->prob))) return rc;
   } else {
-    hipLaunchKernelGGL((k_div<T>), grid, dim3(kUpd), 0, p->stream, g, z0, a0, r, p->prob);
+    hipLaunchKernelGGL((k_div<T>), dim3((unsigned)p->upd_blocks, (unsigned)p->B), dim3(kUpd), 0, p->stream, g,
+                       z0, a0, r, p->prob);
     HIP_LAUNCH_CHECK();
   }
   if ((rc = launch_laplace<T>(p, r, p->phi, p->B, p->prob, fused))) return rc;
   hipEvent_t e0, e1;
   if (timed && (rc = record_event(p, &e0))) return rc;
-  hipLaunchKernelGGL((k_update<T>), grid, dim3(kUpd), 0, p->stream, g, kap, z0, a0, p->phi, z1, a1,
+  const dim3 ugrid((unsigned)p->upd_blocks, (unsigned)p->B);
+  hipLaunchKernelGGL((k_update<T>), ugrid, dim3(kUpd), 0, p->stream, g, kap, z0, a0, p->phi, z1, a1,
                      p->partials, p->prob);
   HIP_LAUNCH_CHECK();
   if (timed && (rc = record_event(p, &e1))) return rc;
@@ -619,6 +644,7 @@ int autotune(ccmf_plan_s* p) {
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   std::array<int, 13> best{};
+  const bool log = std::getenv("CCMF_TUNE_LOG") != nullptr;  // per-candidate timings on stderr
   const bool present[6] = {p->n[2] > 1, p->n[1] > 1, true, p->n[1] > 1, p->n[2] > 1, fused_div_ok(p)};
   p->planes_hint = 0;
   for (int kind = 0; kind < 6; ++kind) {
@@ -627,7 +653,7 @@ int autotune(ccmf_plan_s* p) {
     if (!present[kind] || !is_pow2_len(p->ax[kind == 2 ? 0 : (kind == 1 || kind == 3) ? 1 : 2].n)) continue;
     float best_ms = 1e30f;
     for (int var = 0; var < 2; ++var) {
-      for (int nlc = 1; nlc <= 16; nlc <<= 1) {
+      for (int nlc = 1; nlc <= 32; nlc <<= 1) {
         p->nlc_hint[kind] = nlc;
         p->var_hint[kind] = var;
         if (run_pass<T>(p, kind) != CCMF_OK) continue;  // infeasible width (LDS or threads)
@@ -637,6 +663,7 @@ int autotune(ccmf_plan_s* p) {
         if (hipEventSynchronize(e1) != hipSuccess) break;
         float ms = 0.f;
         hipEventElapsedTime(&ms, e0, e1);
+        if (log) std::fprintf(stderr, "[ccmf tune] pass %d variant %d lines %d: %.1f us\n", kind, var, 2 * nlc, ms / 3 * 1e3);
         if (ms < best_ms) {
           best_ms = ms;
           best[kind] = nlc;
@@ -660,6 +687,7 @@ int autotune(ccmf_plan_s* p) {
       if (hipEventSynchronize(e1) != hipSuccess) break;
       float ms = 0.f;
       hipEventElapsedTime(&ms, e0, e1);
+      if (log) std::fprintf(stderr, "[ccmf tune] fused divergence, %d planes per block: %.1f us\n", planes, ms / 3 * 1e3);
       if (ms < best_ms) {
         best_ms = ms;
         best[12] = planes;
@@ -777,17 +805,19 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
     p->tuned_off = opt.no_autotune != 0;
   }
   p->ev_used = 0;
-  const bool eager = opt.eager != 0 || opt.time_kernels != 0;
+  // HIP events recorded by graph nodes cannot be timed, so timed solves launch eagerly
+  const bool timed = opt.time_kernels != 0;
+  const bool eager = opt.eager != 0 || timed;
   if (eager) {
     bool all_done = false;
     for (int it = 0; it < opt.max_iter && !all_done; ++it) {
-      if ((rc = run_iteration<T>(p, it, opt.time_kernels != 0))) return rc;
+      if ((rc = run_iteration<T>(p, it, timed))) return rc;
       if ((it + 1) % opt.check_every == 0 || it + 1 == opt.max_iter) {
         HIP_TRY(hipMemcpyAsync(p->probh, p->prob, (size_t)p->B * sizeof(Prob), hipMemcpyDeviceToHost, p->stream));
         HIP_TRY(hipStreamSynchronize(p->stream));
         all_done = true;
         for (int64_t b = 0; b < p->B; ++b) all_done = all_done && p->probh[b].done != 0;
-        if (opt.time_kernels && (rc = harvest_events(p))) return rc;
+        if (timed && (rc = harvest_events(p))) return rc;
       }
     }
   } else {
@@ -833,7 +863,7 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
   }
   HIP_TRY(hipMemcpyAsync(p->probh, p->prob, (size_t)p->B * sizeof(Prob), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
-  if (opt.time_kernels && (rc = harvest_events(p))) return rc;
+  if (timed && (rc = harvest_events(p))) return rc;
   int status = CCMF_OK;
   for (int64_t b = 0; b < p->B; ++b) {
     const Prob& P = p->probh[b];
@@ -1170,7 +1200,10 @@ int ccmf_stream_copy(void* dst_dev, const void* src_dev, int64_t nbytes, void* s
   if (!dst_dev || !src_dev || nbytes < 0 || (nbytes % 16) != 0) return fail(CCMF_EINVAL, "bad argument");
   const size_t n16 = (size_t)nbytes / 16;
   if (n16 == 0) return CCMF_OK;
-  const unsigned blocks = (unsigned)std::min<size_t>(8192, (n16 + kThreads - 1) / kThreads);
+  // one 16-byte element per thread over a grid that covers the buffer: blocks are
+  // dispatched in address order, which keeps the set of open DRAM pages small (a
+  // grid-stride loop over a few thousand blocks measured ~25 % slower on MI355X)
+  const unsigned blocks = (unsigned)std::min<size_t>(size_t(1) << 30, (n16 + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(kThreads), 0, reinterpret_cast<hipStream_t>(stream),
                      reinterpret_cast<const uint4*>(src_dev), reinterpret_cast<uint4*>(dst_dev), n16);
   HIP_LAUNCH_CHECK();

@@ -19,11 +19,14 @@
 namespace ccmf {
 
 constexpr int kThreads = 256;
-#ifndef CCMF_UPD_THREADS
-#define CCMF_UPD_THREADS 256
-#endif
 // threads per block (= voxels per tile) of the stencil kernels k_div and k_update
-constexpr int kUpd = CCMF_UPD_THREADS;
+constexpr int kUpd = 256;
+// blocks per problem of the stencil kernels (each walks tiles, see tile_of) and
+// FP64 partial rows per problem.  Measured on MI355X (256^3, FP32): fewer tiles
+// per block make k_update faster by a few percent (4 planes: -4 %), but the
+// extra reduction level that the larger number of partial rows needs costs more
+// than that (one more launch per iteration).
+constexpr int kUpdBlocks = 2048;
 constexpr int kNQ = 16;  // FP64 partial sums per block (13 used)
 
 // indices of the per-block FP64 partial sums
@@ -202,6 +205,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 //   xi^{k+1}  = 2(1-delta) xi^{k+1/2} - (1-2delta) e^k
 //   z'        = v^k + rho^k xi^{k+1};  alpha' = min(1, gamma/|z'|)
 // ---------------------------------------------------------------------------
+// Each block walks g.tiles_per_blk tiles (see tile_of) and writes one FP64
+// partial row, reduced by k_finish.
 template <typename T>
 __global__ void __launch_bounds__(kUpd)
 k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __restrict__ a,
@@ -303,12 +308,42 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
     if (lane == 0) red[wv][q] = sq;
   }
   __syncthreads();
-  if (threadIdx.x < kNQU) {
+  if (threadIdx.x < kNQ) {   // whole row, unused columns zero
     double sq = 0.0;
+    if (threadIdx.x < kNQU) {
 #pragma unroll
-    for (int w = 0; w < kUpd / 64; ++w) sq += red[w][threadIdx.x];
+      for (int w = 0; w < kUpd / 64; ++w) sq += red[w][threadIdx.x];
+    }
     partials[((size_t)b * gridDim.x + lb) * kNQ + threadIdx.x] = sq;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order sum of `nrows` partial rows of kNQ doubles by a block of NT
+// threads, read as one contiguous array so every wavefront load is coalesced:
+// thread t always takes column t % kNQ, rows in increasing order; lanes of one
+// column are combined by shuffles and the wavefronts in order.  Result in
+// out[0..kNQU) of the shared array (valid after the call for all threads).
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ void block_sum_rows(const double* __restrict__ rows, int nrows, double* out) {
+  static_assert(NT % 64 == 0 && kNQ == 16, "layout");
+  __shared__ double red[NT / 64][kNQ];
+  double acc = 0.0;
+  const int total = nrows * kNQ;
+  for (int e = threadIdx.x; e < total; e += NT) acc += rows[e];
+  acc += __shfl_down(acc, 32, 64);
+  acc += __shfl_down(acc, 16, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane < kNQ) red[wv][lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < kNQ) {
+    double sq = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) sq += red[w][threadIdx.x];
+    out[threadIdx.x] = sq;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -327,29 +362,8 @@ k_finish(uint32_t N, int nparts, const double* __restrict__ partials, Prob* __re
   // the iteration index lives on the device, so a captured chunk of iterations
   // can be replayed unchanged
   const int it = P.k;
-  // fixed-order reduction: per-thread rows in order, wavefront shuffle trees,
-  // then the waves in order
-  double acc[kNQU];
-#pragma unroll
-  for (int q = 0; q < kNQU; ++q) acc[q] = 0.0;
-  const double* pp = partials + (size_t)b * nparts * kNQ;
-  for (int i = threadIdx.x; i < nparts; i += kFinishThreads) {
-#pragma unroll
-    for (int q = 0; q < kNQU; ++q) acc[q] += pp[(size_t)i * kNQ + q];
-  }
-  __shared__ double red[kFinishThreads / 64][kNQU];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < kNQU; ++q) {
-    const double sq = wave_sum<double>(acc[q]);
-    if (lane == 0) red[wv][q] = sq;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kFinishThreads / 64; ++w)
-#pragma unroll
-      for (int q = 0; q < kNQU; ++q) red[0][q] += red[w][q];
-  }
+  __shared__ double red[1][kNQ];
+  block_sum_rows<kFinishThreads>(partials + (size_t)b * nparts * kNQ, nparts, red[0]);
   if (threadIdx.x != 0) return;
   const double invN = 1.0 / (double)N;
   const double res = sqrt(red[0][Q_RES2] * invN);

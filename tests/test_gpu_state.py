@@ -177,3 +177,20 @@ def test_state_errors():
     p.solve([(1, 0, 0), (0, 1, 0)], tol=1e-6)
     with pytest.raises(CcmfError, match="warm start"):
         p.solve([(1, 0, 0)], tol=1e-6, warm_start=True)
+
+
+# --- kernel timing inside the replayed graph --------------------------------------
+
+@pytest.mark.parametrize("eager", [False, True])
+def test_timed_solve_matches_untimed(eager):
+    banner(f"timed solve eager={eager}")
+    g = spheres((16, 12, 10), 4)
+    p = plan_of(g, torch.float32)
+    ref = p.solve([(1, 0, 0), XB], tol=1e-5, max_iter=3000)
+    p.kernel_times()
+    r = p.solve([(1, 0, 0), XB], tol=1e-5, max_iter=3000, time_kernels=True, eager=eager)
+    assert np.array_equal(r.geff, ref.geff) and np.array_equal(r.iterations, ref.iterations)
+    avg, count, per_problem = p.kernel_times()
+    # one timed launch per iteration (graph replays run whole chunks of 32)
+    assert count >= int(r.iterations.max()) and avg > 0.0
+    assert per_problem == (15 * 4 + 8) * g.size
