@@ -32,9 +32,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 # Fabric traffic of the fused update kernel per launch and active problem on the 256^3 FP32
-# workload: rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scale factors from the 2 GiB copy
-# kernel), see profiles/k_update_ud_fibres256_f32_traffic.md.  None once the kernel changes.
-K_UPDATE_TRAFFIC_C2 = None
+# workload: rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by what they read for the 2 GiB copy
+# kernel, see profiles/k_update_ud_fibres256_f32_traffic.md.  None once the kernel changes.
+K_UPDATE_TRAFFIC_C2 = 1.341e9
 
 
 def log(msg):
@@ -198,8 +198,10 @@ def main():
     last = results[-1]
 
     esz = 8 if dtype == "f64" else 4
-    # bytes per voxel and iteration over all kernels of one iteration (see design notes)
-    iter_bytes = {8: 272.0, 4: 160.0}[esz]
+    # algorithmic bytes per voxel and iteration over all kernels of one iteration
+    # (power-of-two n3: divergence fused with the forward k pass):
+    # div+k 7s+s, j fwd 2s, i s+8, j inv 16, k inv 16, update 15s+8
+    iter_bytes = {8: 256.0, 4: 152.0}[esz]
     iter_frac = value * iter_bytes / 1e9 / HBM_PEAK_GBPS
 
     accuracy = {}
@@ -250,8 +252,11 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": (K_UPDATE_TRAFFIC_C2 if args.workload == "c2" else None),
-            "traffic_unit": "bytes per launch and active problem (rocprofv3 FETCH_SIZE, WRITE_SIZE)",
+            # per launch like `achieved`: the per-problem figure times the mean number of
+            # active problems per launch of the timed region
+            "traffic": (K_UPDATE_TRAFFIC_C2 * tot_iters / launches
+                        if args.workload == "c2" and K_UPDATE_TRAFFIC_C2 and launches else None),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": avg_ms,
             "launches": launches,
             "bytes_per_launch_per_problem": bytes_per_problem,
