@@ -297,12 +297,22 @@ int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, 
   return CCMF_OK;
 }
 
+// Plan variant of a pass: the autotuner's choice, overridden by the diagnostic
+// environment variable CCMF_FFT_VARIANT (0, 1 or 2) when it is set.
+int variant_of(const ccmf_plan_s* p, int kind) {
+  const char* env = std::getenv("CCMF_FFT_VARIANT");
+  if (env != nullptr && env[0] >= '0' && env[0] <= '2' && env[1] == '\0') return env[0] - '0';
+  return kind >= 0 ? p->var_hint[kind] : 0;
+}
+
 template <typename TI, typename TO, typename TC, int N>
 int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
               bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob, int kind) {
-  const int var = kind >= 0 ? p->var_hint[kind] : 0;
+  const int var = variant_of(p, kind);
   if (var == 1)
     return launch_p2v<TI, TO, TC, N, 1>(p, in, out, count, A, outers, contig, middle, twp, s1, s2, s3, prob, kind);
+  if (var == 2)
+    return launch_p2v<TI, TO, TC, N, 2>(p, in, out, count, A, outers, contig, middle, twp, s1, s2, s3, prob, kind);
   return launch_p2v<TI, TO, TC, N, 0>(p, in, out, count, A, outers, contig, middle, twp, s1, s2, s3, prob, kind);
 }
 
@@ -425,7 +435,9 @@ int launch_div_p2v(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, 
 
 template <typename T, int N>
 int launch_div_p2(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, const Prob* prob) {
-  if (p->var_hint[5] == 1) return launch_div_p2v<T, N, 1>(p, z, a, r, count, prob);
+  const int var = variant_of(p, 5);
+  if (var == 1) return launch_div_p2v<T, N, 1>(p, z, a, r, count, prob);
+  if (var == 2) return launch_div_p2v<T, N, 2>(p, z, a, r, count, prob);
   return launch_div_p2v<T, N, 0>(p, z, a, r, count, prob);
 }
 
@@ -652,7 +664,7 @@ int autotune(ccmf_plan_s* p) {
     best[6 + kind] = 0;
     if (!present[kind] || !is_pow2_len(p->ax[kind == 2 ? 0 : (kind == 1 || kind == 3) ? 1 : 2].n)) continue;
     float best_ms = 1e30f;
-    for (int var = 0; var < 2; ++var) {
+    for (int var = 0; var < 3; ++var) {
       for (int nlc = 1; nlc <= 32; nlc <<= 1) {
         p->nlc_hint[kind] = nlc;
         p->var_hint[kind] = var;

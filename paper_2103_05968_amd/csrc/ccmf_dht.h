@@ -324,6 +324,19 @@ __device__ __forceinline__ void fft_line_p2(pow2::CX<TC>* line, int t, const pow
         line[pidx<N, V>(pow2::stage_out_pos<N, E, P::R2, NS>(t, m, r))] = v[m + r * (E / P::R2)];
     __syncthreads();
   }
+  if constexpr (P::R3 > 0) {
+    constexpr int NS = P::R0 * P::R1 * P::R2;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = line[pidx<N, V>(t + TPL * e)];
+    pow2::stage_compute<TC, N, E, P::R3, NS>(v, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E / P::R3; ++m)
+#pragma unroll
+      for (int r = 0; r < P::R3; ++r)
+        line[pidx<N, V>(pow2::stage_out_pos<N, E, P::R3, NS>(t, m, r))] = v[m + r * (E / P::R3)];
+    __syncthreads();
+  }
 }
 
 template <typename TC, int N, int V>

@@ -103,33 +103,46 @@ __host__ __device__ __forceinline__ void dft(CX<T>* v) {
   if constexpr (R == 16) dft16(v);
 }
 
-// Stage plans: elements per thread E and radices R0, R1, R2 (0 = no stage).
+// Stage plans: elements per thread E and radices R0..R3 (0 = no stage).
 // Variant V = 0 uses the largest radices; V = 1 halves E where possible (more
-// threads per line and fewer registers per thread).  The autotuner picks one.
+// threads per line and fewer registers per thread); V = 2 uses E = 4 (radix-4
+// stages, four times the threads of V = 0 for the same LDS tile) up to 256.
+// The autotuner picks one.
 template <int N, int V = 0>
 struct Plan;
-template <> struct Plan<2, 0>    { static constexpr int E = 2,  R0 = 2,  R1 = 0,  R2 = 0; };
-template <> struct Plan<4, 0>    { static constexpr int E = 4,  R0 = 4,  R1 = 0,  R2 = 0; };
-template <> struct Plan<8, 0>    { static constexpr int E = 8,  R0 = 8,  R1 = 0,  R2 = 0; };
-template <> struct Plan<16, 0>   { static constexpr int E = 16, R0 = 16, R1 = 0,  R2 = 0; };
-template <> struct Plan<32, 0>   { static constexpr int E = 8,  R0 = 8,  R1 = 4,  R2 = 0; };
-template <> struct Plan<64, 0>   { static constexpr int E = 8,  R0 = 8,  R1 = 8,  R2 = 0; };
-template <> struct Plan<128, 0>  { static constexpr int E = 16, R0 = 16, R1 = 8,  R2 = 0; };
-template <> struct Plan<256, 0>  { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 0; };
-template <> struct Plan<512, 0>  { static constexpr int E = 8,  R0 = 8,  R1 = 8,  R2 = 8; };
-template <> struct Plan<1024, 0> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 4; };
-template <> struct Plan<2048, 0> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 8; };
-template <> struct Plan<2, 1>    { static constexpr int E = 2,  R0 = 2,  R1 = 0,  R2 = 0; };
-template <> struct Plan<4, 1>    { static constexpr int E = 2,  R0 = 2,  R1 = 2,  R2 = 0; };
-template <> struct Plan<8, 1>    { static constexpr int E = 4,  R0 = 4,  R1 = 2,  R2 = 0; };
-template <> struct Plan<16, 1>   { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 0; };
-template <> struct Plan<32, 1>   { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 2; };
-template <> struct Plan<64, 1>   { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 4; };
-template <> struct Plan<128, 1>  { static constexpr int E = 8,  R0 = 8,  R1 = 8,  R2 = 2; };
-template <> struct Plan<256, 1>  { static constexpr int E = 8,  R0 = 8,  R1 = 8,  R2 = 4; };
-template <> struct Plan<512, 1>  { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 2; };
-template <> struct Plan<1024, 1> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 4; };
-template <> struct Plan<2048, 1> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 8; };
+template <> struct Plan<2, 0>    { static constexpr int E = 2,  R0 = 2,  R1 = 0,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<4, 0>    { static constexpr int E = 4,  R0 = 4,  R1 = 0,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<8, 0>    { static constexpr int E = 8,  R0 = 8,  R1 = 0,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<16, 0>   { static constexpr int E = 16, R0 = 16, R1 = 0,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<32, 0>   { static constexpr int E = 8,  R0 = 8,  R1 = 4,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<64, 0>   { static constexpr int E = 8,  R0 = 8,  R1 = 8,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<128, 0>  { static constexpr int E = 16, R0 = 16, R1 = 8,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<256, 0>  { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<512, 0>  { static constexpr int E = 8,  R0 = 8,  R1 = 8,  R2 = 8; static constexpr int R3 = 0; };
+template <> struct Plan<1024, 0> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 4; static constexpr int R3 = 0; };
+template <> struct Plan<2048, 0> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 8; static constexpr int R3 = 0; };
+template <> struct Plan<2, 1>    { static constexpr int E = 2,  R0 = 2,  R1 = 0,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<4, 1>    { static constexpr int E = 2,  R0 = 2,  R1 = 2,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<8, 1>    { static constexpr int E = 4,  R0 = 4,  R1 = 2,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<16, 1>   { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<32, 1>   { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 2; static constexpr int R3 = 0; };
+template <> struct Plan<64, 1>   { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 4; static constexpr int R3 = 0; };
+template <> struct Plan<128, 1>  { static constexpr int E = 8,  R0 = 8,  R1 = 8,  R2 = 2; static constexpr int R3 = 0; };
+template <> struct Plan<256, 1>  { static constexpr int E = 8,  R0 = 8,  R1 = 8,  R2 = 4; static constexpr int R3 = 0; };
+template <> struct Plan<512, 1>  { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 2; static constexpr int R3 = 0; };
+template <> struct Plan<1024, 1> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 4; static constexpr int R3 = 0; };
+template <> struct Plan<2048, 1> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 8; static constexpr int R3 = 0; };
+template <> struct Plan<2, 2>    { static constexpr int E = 2,  R0 = 2,  R1 = 0,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<4, 2>    { static constexpr int E = 4,  R0 = 4,  R1 = 0,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<8, 2>    { static constexpr int E = 4,  R0 = 4,  R1 = 2,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<16, 2>   { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 0; static constexpr int R3 = 0; };
+template <> struct Plan<32, 2>   { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 2; static constexpr int R3 = 0; };
+template <> struct Plan<64, 2>   { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 4; static constexpr int R3 = 0; };
+template <> struct Plan<128, 2>  { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 4; static constexpr int R3 = 2; };
+template <> struct Plan<256, 2>  { static constexpr int E = 4,  R0 = 4,  R1 = 4,  R2 = 4; static constexpr int R3 = 4; };
+template <> struct Plan<512, 2>  { static constexpr int E = 8,  R0 = 8,  R1 = 8,  R2 = 8; static constexpr int R3 = 0; };
+template <> struct Plan<1024, 2> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 4; static constexpr int R3 = 0; };
+template <> struct Plan<2048, 2> { static constexpr int E = 16, R0 = 16, R1 = 16, R2 = 8; static constexpr int R3 = 0; };
 
 // One Stockham stage on the E values a thread holds.  Before the stage thread t
 // (0 <= t < TPL = N/E) holds x[t + TPL*e]; butterfly m of the thread (E/R of

@@ -314,3 +314,28 @@ def test_not_converged_is_reported():
     assert not r.converged and r.iterations[0, 0] == 7
     with pytest.raises(CcmfError):
         p.solve([(1, 0, 0)], tol=1e-12, max_iter=7, raise_not_converged=True)
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2"])
+def test_fft_plan_variants(variant, rng, monkeypatch):
+    """Every register-blocked FFT plan variant (forced through the diagnostic
+    CCMF_FFT_VARIANT) in every pass: single Hartley passes against numpy, the
+    pseudo-inverse against the oracle, and a fixed-K solve against the oracle."""
+    banner(f"fft plan variant {variant}")
+    monkeypatch.setenv("CCMF_FFT_VARIANT", variant)
+    for dims in [(32, 16, 8), (4, 128, 256), (256, 2, 4)]:
+        for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 2e-5)):
+            p = plan_of(np.ones(dims), dtype)
+            x = rng.standard_normal((2,) + dims)
+            xt = torch.as_tensor(x, dtype=dtype, device=DEV)
+            for axis in range(3):
+                got = p.hartley_axis(xt, axis).double().cpu().numpy()
+                want = dht_axis_np(x, axis + 1)
+                assert np.abs(got - want).max() <= tol * np.abs(want).max() * 8, (dims, axis)
+            got = p.laplace_pinv(xt).double().cpu().numpy()
+            want = O.laplace_pinv(x[0])
+            assert np.abs(got[0] - want).max() <= 5 * tol * np.abs(want).max(), dims
+        gamma = M.boolean_spheres(dims, 2.0, 0.2, 5.0, 1.0, seed=3)
+        res = plan_of(gamma).solve([(0.48, 0.6, 0.64)], tol=1e-300, max_iter=12, autotune=False)
+        ora = O.admm_solve(gamma, (0.48, 0.6, 0.64), tol=1e-300, max_iter=12)
+        assert abs(res.geff[0, 0] - ora.geff) <= 1e-10 * ora.geff, dims
