@@ -33,6 +33,13 @@
  *    message in ccmf_last_error()); CCMF_NOT_CONVERGED (= 1) is a warning:
  *    all outputs are written from the last iterate.
  *  - A plan is not thread safe; distinct plans are independent.
+ *
+ * Diagnostic environment variables (read by the library, never needed):
+ *  - CCMF_TUNE_LOG: when set, the transform-tile autotuner prints every
+ *    candidate's time to stderr.
+ *  - CCMF_FFT_VARIANT = 0, 1 or 2: forces one register-blocked FFT plan variant
+ *    in every power-of-two transform pass instead of the autotuner's choice
+ *    (results agree to rounding; used to test each variant).
  */
 #ifndef CCMF_H_
 #define CCMF_H_
