@@ -51,6 +51,7 @@ struct Axis {
   int n = 1;
   std::vector<int> radix;
   void* tw[2] = {nullptr, nullptr};  // complex twiddles exp(-2 pi i t / n), t < n: [0] double, [1] float
+  void* tws[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};  // stage-major, per plan variant
   void* s[2] = {nullptr, nullptr};   // 4 sin^2(pi q / n), q < n: [0] double, [1] float
 };
 
@@ -119,7 +120,6 @@ struct ccmf_plan_s {
   // (0 forward k, 1 forward j, 2 fused i, 3 inverse j, 4 inverse k); 0 = rule of thumb
   // kind 5: r = div^- A* w fused with the forward k pass
   int nlc_hint[6] = {0, 0, 0, 0, 0, 0};
-  int var_hint[6] = {0, 0, 0, 0, 0, 0};   // plan variant (ccmf_fft_pow2.h) per pass
   int planes_hint = 0;                    // planes walked per block by the fused kernel
   int64_t tuned_B = 0;
   bool tuned_off = false;
@@ -141,6 +141,7 @@ struct ccmf_plan_s {
     for (int c = 0; c < 3; ++c) {
       for (int q = 0; q < 2; ++q) {
         hipFree(ax[c].tw[q]);
+        for (int v = 0; v < 3; ++v) hipFree(ax[c].tws[q][v]);
         hipFree(ax[c].s[q]);
       }
     }
@@ -197,6 +198,31 @@ Geo make_geo(const ccmf_plan_s* p) {
   return g;
 }
 
+bool is_pow2_len(int n);
+
+template <int V>
+bool stage_twiddles_v(int n, const double* w, double* out) {
+  switch (n) {
+    case 2: pow2::stage_twiddles<2, V>(w, out); return true;
+    case 4: pow2::stage_twiddles<4, V>(w, out); return true;
+    case 8: pow2::stage_twiddles<8, V>(w, out); return true;
+    case 16: pow2::stage_twiddles<16, V>(w, out); return true;
+    case 32: pow2::stage_twiddles<32, V>(w, out); return true;
+    case 64: pow2::stage_twiddles<64, V>(w, out); return true;
+    case 128: pow2::stage_twiddles<128, V>(w, out); return true;
+    case 256: pow2::stage_twiddles<256, V>(w, out); return true;
+    case 512: pow2::stage_twiddles<512, V>(w, out); return true;
+    case 1024: pow2::stage_twiddles<1024, V>(w, out); return true;
+    case 2048: pow2::stage_twiddles<2048, V>(w, out); return true;
+    default: return false;
+  }
+}
+
+bool stage_twiddles_of(int n, int v, const double* w, double* out) {
+  return v == 0 ? stage_twiddles_v<0>(n, w, out) : v == 1 ? stage_twiddles_v<1>(n, w, out)
+                                                          : stage_twiddles_v<2>(n, w, out);
+}
+
 int upload_axis(Axis& ax, int n) {
   ax.n = n;
   ax.radix = factor_radices(n);
@@ -219,6 +245,18 @@ int upload_axis(Axis& ax, int n) {
   HIP_TRY(hipMemcpy(ax.s[0], sv.data(), sv.size() * sizeof(double), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ax.tw[1], tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ax.s[1], sv32.data(), sv32.size() * sizeof(float), hipMemcpyHostToDevice));
+  if (is_pow2_len(n)) {
+    // the same values, reordered stage-major for each register-blocked plan variant
+    std::vector<double> st(2 * (size_t)n);
+    for (int v = 0; v < 3; ++v) {
+      if (!stage_twiddles_of(n, v, tw.data(), st.data())) return fail(CCMF_EINVAL, "no FFT plan for length %d", n);
+      std::vector<float> st32(st.begin(), st.end());
+      HIP_TRY(hipMalloc(&ax.tws[0][v], st.size() * sizeof(double)));
+      HIP_TRY(hipMalloc(&ax.tws[1][v], st32.size() * sizeof(float)));
+      HIP_TRY(hipMemcpy(ax.tws[0][v], st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(ax.tws[1][v], st32.data(), st32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+  }
   return CCMF_OK;
 }
 
@@ -297,23 +335,30 @@ int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, 
   return CCMF_OK;
 }
 
-// Plan variant of a pass: the autotuner's choice, overridden by the diagnostic
-// environment variable CCMF_FFT_VARIANT (0, 1 or 2) when it is set.
-int variant_of(const ccmf_plan_s* p, int kind) {
+// Plan variant of a pass.  The variant changes the radix decomposition, hence
+// the rounding, so it is a fixed function of the pass (never timed): results are
+// reproducible and a batched solve equals the single solves bit for bit.  From
+// the measured 256-point passes on MI355X: FP32 lines radix-16 (variant 0), FP64
+// lines radix-8/4 (variant 1), the fused divergence pass radix-4 (variant 2).
+// The diagnostic environment variable CCMF_FFT_VARIANT (0, 1 or 2) overrides it.
+int variant_of(int kind, bool fp64) {
   const char* env = std::getenv("CCMF_FFT_VARIANT");
   if (env != nullptr && env[0] >= '0' && env[0] <= '2' && env[1] == '\0') return env[0] - '0';
-  return kind >= 0 ? p->var_hint[kind] : 0;
+  if (kind == 5) return 2;
+  return fp64 ? 1 : 0;
 }
 
 template <typename TI, typename TO, typename TC, int N>
 int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
-              bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob, int kind) {
-  const int var = variant_of(p, kind);
+              bool middle, void* const* tws, const TC* s1, const TC* s2, const TC* s3, const Prob* prob,
+              int kind) {
+  // tws: the stage-major twiddle tables of the three plan variants for this precision
+  const int var = variant_of(kind, sizeof(TC) == 8);
   if (var == 1)
-    return launch_p2v<TI, TO, TC, N, 1>(p, in, out, count, A, outers, contig, middle, twp, s1, s2, s3, prob, kind);
+    return launch_p2v<TI, TO, TC, N, 1>(p, in, out, count, A, outers, contig, middle, tws[1], s1, s2, s3, prob, kind);
   if (var == 2)
-    return launch_p2v<TI, TO, TC, N, 2>(p, in, out, count, A, outers, contig, middle, twp, s1, s2, s3, prob, kind);
-  return launch_p2v<TI, TO, TC, N, 0>(p, in, out, count, A, outers, contig, middle, twp, s1, s2, s3, prob, kind);
+    return launch_p2v<TI, TO, TC, N, 2>(p, in, out, count, A, outers, contig, middle, tws[2], s1, s2, s3, prob, kind);
+  return launch_p2v<TI, TO, TC, N, 0>(p, in, out, count, A, outers, contig, middle, tws[0], s1, s2, s3, prob, kind);
 }
 
 // Launch one Hartley pass along `axis` over `count` fields: load TI from `in`,
@@ -363,17 +408,17 @@ int launch_hartley(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, int axi
   const TC* s3 = reinterpret_cast<const TC*>(p->ax[2].s[q]);
   if (is_pow2_len(A.n)) {
     switch (A.n) {
-      case 2: return launch_p2<TI, TO, TC, 2>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 4: return launch_p2<TI, TO, TC, 4>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 8: return launch_p2<TI, TO, TC, 8>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 16: return launch_p2<TI, TO, TC, 16>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 32: return launch_p2<TI, TO, TC, 32>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 64: return launch_p2<TI, TO, TC, 64>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 128: return launch_p2<TI, TO, TC, 128>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 256: return launch_p2<TI, TO, TC, 256>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 512: return launch_p2<TI, TO, TC, 512>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 1024: return launch_p2<TI, TO, TC, 1024>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
-      case 2048: return launch_p2<TI, TO, TC, 2048>(p, in, out, count, A, outers, contig, middle, ax.tw[q], s1, s2, s3, prob, kind);
+      case 2: return launch_p2<TI, TO, TC, 2>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 4: return launch_p2<TI, TO, TC, 4>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 8: return launch_p2<TI, TO, TC, 8>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 16: return launch_p2<TI, TO, TC, 16>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 32: return launch_p2<TI, TO, TC, 32>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 64: return launch_p2<TI, TO, TC, 64>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 128: return launch_p2<TI, TO, TC, 128>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 256: return launch_p2<TI, TO, TC, 256>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 512: return launch_p2<TI, TO, TC, 512>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 1024: return launch_p2<TI, TO, TC, 1024>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 2048: return launch_p2<TI, TO, TC, 2048>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
       default: break;
     }
   }
@@ -426,7 +471,7 @@ int launch_div_p2v(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, 
   D.ichunks = (D.n1 + planes - 1) / planes;
   D.vec = ((reinterpret_cast<uintptr_t>(r) & 15) == 0 && N * (int)sizeof(T) >= 16) ? 1 : 0;
   dim3 grid((unsigned)(D.jtiles * D.ichunks), (unsigned)count);
-  const pow2::CX<T>* tw = reinterpret_cast<const pow2::CX<T>*>(p->ax[2].tw[prec_index<T>()]);
+  const pow2::CX<T>* tw = reinterpret_cast<const pow2::CX<T>*>(p->ax[2].tws[prec_index<T>()][V]);
   hipLaunchKernelGGL((k_div_hartley_p2<T, N, V>), grid, dim3((unsigned)(nlc * TPL)), lds, p->stream, z, a, r, tw,
                      D, prob);
   HIP_LAUNCH_CHECK();
@@ -435,7 +480,7 @@ int launch_div_p2v(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, 
 
 template <typename T, int N>
 int launch_div_p2(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, const Prob* prob) {
-  const int var = variant_of(p, 5);
+  const int var = variant_of(5, sizeof(T) == 8);
   if (var == 1) return launch_div_p2v<T, N, 1>(p, z, a, r, count, prob);
   if (var == 2) return launch_div_p2v<T, N, 2>(p, z, a, r, count, prob);
   return launch_div_p2v<T, N, 0>(p, z, a, r, count, prob);
@@ -643,7 +688,6 @@ int autotune(ccmf_plan_s* p) {
     if (it != g_tune_cache.end()) {
       for (int k = 0; k < 6; ++k) {
         p->nlc_hint[k] = it->second[k];
-        p->var_hint[k] = it->second[6 + k];
       }
       p->planes_hint = it->second[12];
       p->tuned_B = p->B;
@@ -661,30 +705,24 @@ int autotune(ccmf_plan_s* p) {
   p->planes_hint = 0;
   for (int kind = 0; kind < 6; ++kind) {
     best[kind] = 0;
-    best[6 + kind] = 0;
     if (!present[kind] || !is_pow2_len(p->ax[kind == 2 ? 0 : (kind == 1 || kind == 3) ? 1 : 2].n)) continue;
     float best_ms = 1e30f;
-    for (int var = 0; var < 3; ++var) {
-      for (int nlc = 1; nlc <= 32; nlc <<= 1) {
-        p->nlc_hint[kind] = nlc;
-        p->var_hint[kind] = var;
-        if (run_pass<T>(p, kind) != CCMF_OK) continue;  // infeasible width (LDS or threads)
-        hipEventRecord(e0, p->stream);
-        for (int rep = 0; rep < 3; ++rep) run_pass<T>(p, kind);
-        hipEventRecord(e1, p->stream);
-        if (hipEventSynchronize(e1) != hipSuccess) break;
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (log) std::fprintf(stderr, "[ccmf tune] pass %d variant %d lines %d: %.1f us\n", kind, var, 2 * nlc, ms / 3 * 1e3);
-        if (ms < best_ms) {
-          best_ms = ms;
-          best[kind] = nlc;
-          best[6 + kind] = var;
-        }
+    for (int nlc = 1; nlc <= 32; nlc <<= 1) {
+      p->nlc_hint[kind] = nlc;
+      if (run_pass<T>(p, kind) != CCMF_OK) continue;  // infeasible width (LDS or threads)
+      hipEventRecord(e0, p->stream);
+      for (int rep = 0; rep < 3; ++rep) run_pass<T>(p, kind);
+      hipEventRecord(e1, p->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) break;
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (log) std::fprintf(stderr, "[ccmf tune] pass %d lines %d: %.1f us\n", kind, 2 * nlc, ms / 3 * 1e3);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best[kind] = nlc;
       }
     }
     p->nlc_hint[kind] = best[kind];
-    p->var_hint[kind] = best[6 + kind];
   }
   // planes walked per block by the fused divergence kernel
   best[12] = 0;
@@ -808,7 +846,7 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
   if (p->tuned_B != p->B || (opt.no_autotune != 0) != p->tuned_off) {
     p->drop_graph();
     if (opt.no_autotune) {
-      for (int k = 0; k < 6; ++k) p->nlc_hint[k] = p->var_hint[k] = 0;
+      for (int k = 0; k < 6; ++k) p->nlc_hint[k] = 0;
       p->planes_hint = 0;
       p->tuned_B = p->B;
     } else if ((rc = autotune<T>(p))) {

@@ -107,7 +107,7 @@ __host__ __device__ __forceinline__ void dft(CX<T>* v) {
 // Variant V = 0 uses the largest radices; V = 1 halves E where possible (more
 // threads per line and fewer registers per thread); V = 2 uses E = 4 (radix-4
 // stages, four times the threads of V = 0 for the same LDS tile) up to 256.
-// The autotuner picks one.
+// Each pass uses a fixed variant (the launch code's variant_of).
 template <int N, int V = 0>
 struct Plan;
 template <> struct Plan<2, 0>    { static constexpr int E = 2,  R0 = 2,  R1 = 0,  R2 = 0; static constexpr int R3 = 0; };
@@ -147,8 +147,17 @@ template <> struct Plan<2048, 2> { static constexpr int E = 16, R0 = 16, R1 = 16
 // One Stockham stage on the E values a thread holds.  Before the stage thread t
 // (0 <= t < TPL = N/E) holds x[t + TPL*e]; butterfly m of the thread (E/R of
 // them) is u = t + TPL*m with inputs x[u + r*N/R] = element m + r*(E/R).
-// Twiddles: W_N^(r * (u mod Ns) * N/(Ns R)) from the table tw[j] = W_N^j.
+// Twiddles: W_N^(r * k * N/(Ns R)), k = u mod Ns, read from a stage-major table
+// (stage_twiddle_index): the entries of one stage and one r are consecutive in
+// k, so the lanes of a wavefront read consecutive LDS words (a plain table
+// W_N^j read at stride r*k hits the same LDS bank from many lanes).
 // Results go to position (u / Ns) * Ns * R + (u mod Ns) + r * Ns of the line.
+// Position of W_N^(r k N/(NS R)) (1 <= r < R, 0 <= k < NS) in the stage-major
+// table: the stages before this one hold sum (R_s - 1) NS_s = NS - 1 entries.
+__host__ __device__ __forceinline__ constexpr int stage_twiddle_index(int NS, int r, int k) {
+  return (NS - 1) + (r - 1) * NS + k;
+}
+
 template <typename T, int N, int E, int R, int NS>
 __host__ __device__ __forceinline__ void stage_compute(CX<T>* v, int t, const CX<T>* __restrict__ tw) {
   constexpr int TPL = N / E;
@@ -162,7 +171,7 @@ __host__ __device__ __forceinline__ void stage_compute(CX<T>* v, int t, const CX
       const int u = t + TPL * m;
       const int k = u & (NS - 1);
 #pragma unroll
-      for (int r = 1; r < R; ++r) b[r] = mul(b[r], tw[r * k * (N / (NS * R))]);
+      for (int r = 1; r < R; ++r) b[r] = mul(b[r], tw[stage_twiddle_index(NS, r, k)]);
     }
     dft<T, R>(b);
 #pragma unroll
@@ -175,6 +184,28 @@ __host__ __device__ __forceinline__ int stage_out_pos(int t, int m, int r) {
   constexpr int TPL = N / E;
   const int u = t + TPL * m;
   return (u / NS) * NS * R + (u & (NS - 1)) + r * NS;
+}
+
+// Stage-major twiddle table of plan <N, V> from the plain table w[j] = W_N^j
+// (interleaved re, im; n entries): out[2 idx], out[2 idx + 1] = W_N^(r k N/(NS R))
+// at idx = stage_twiddle_index(NS, r, k).  N entries (the last one unused, zero).
+template <int N, int V>
+void stage_twiddles(const double* w, double* out) {
+  using P = Plan<N, V>;
+  const int radices[4] = {P::R0, P::R1, P::R2, P::R3};
+  for (int j = 0; j < 2 * N; ++j) out[j] = 0.0;
+  int ns = 1;
+  for (int st = 0; st < 4 && radices[st] > 0; ++st) {
+    const int R = radices[st];
+    for (int r = 1; r < R; ++r)
+      for (int k = 0; k < ns; ++k) {
+        const int idx = stage_twiddle_index(ns, r, k);
+        const int j = r * k * (N / (ns * R));
+        out[2 * idx] = w[2 * j];
+        out[2 * idx + 1] = w[2 * j + 1];
+      }
+    ns *= R;
+  }
 }
 
 }  // namespace pow2
