@@ -46,3 +46,14 @@ def test_error_paths_without_device():
     assert lib.ccmf_setup(ctypes.byref(h), dims, 1, 7, ctypes.c_void_p(1), None) == _lib.CCMF_EINVAL
     assert lib.ccmf_solve(None, None, 1, 1e-4, None, None, None, None, None, None, None) == _lib.CCMF_EINVAL
     assert lib.ccmf_stream_copy(ctypes.c_void_p(1), ctypes.c_void_p(1), 15, None) == _lib.CCMF_EINVAL
+    # entry points that take a plan reject a null plan before touching the device
+    d = ctypes.c_double()
+    assert lib.ccmf_grad_kappa(None, ctypes.byref(d), ctypes.c_void_p(1)) == _lib.CCMF_EINVAL
+    assert lib.ccmf_certificate(None, ctypes.byref(d), None) == _lib.CCMF_EINVAL
+    assert lib.ccmf_mean_flux(None, ctypes.byref(d)) == _lib.CCMF_EINVAL
+    assert lib.ccmf_get_state(None, None, None, None, None) == _lib.CCMF_EINVAL
+    k = ctypes.c_int32()
+    assert lib.ccmf_set_state(None, 1, ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.byref(d),
+                              ctypes.byref(k)) == _lib.CCMF_EINVAL
+    assert lib.ccmf_laplace_pinv(None, ctypes.c_void_p(1), ctypes.c_void_p(1), 1) == _lib.CCMF_EINVAL
+    assert lib.ccmf_kernel_times(None, None, None, None) == _lib.CCMF_EINVAL
