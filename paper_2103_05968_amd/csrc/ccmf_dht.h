@@ -397,7 +397,7 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
     if constexpr (CONTIG) {
       // rows: V consecutive samples of both rows of a pair per thread
       constexpr int VW = 16 / sizeof(TI);
-      constexpr int CH = N / VW;
+      constexpr int CH = N >= VW ? N / VW : 1;  // the host enables vector IO only for N >= VW
       for (int e = threadIdx.x; e < (nl >> 1) * CH; e += blockDim.x) {
         const int pr = e / CH, s0 = (e & (CH - 1)) * VW;
         VecT<TI, VW> va, vb;
@@ -460,7 +460,7 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
   if (A.vec) {
     if constexpr (CONTIG) {
       constexpr int VW = 16 / sizeof(TO);
-      constexpr int CH = N / VW;
+      constexpr int CH = N >= VW ? N / VW : 1;
       for (int e = threadIdx.x; e < (nl >> 1) * CH; e += blockDim.x) {
         const int pr = e / CH, s0 = (e & (CH - 1)) * VW;
         VecT<TO, VW> va, vb;
@@ -575,7 +575,7 @@ k_div_hartley_p2(const T* __restrict__ z, const T* __restrict__ a, T* __restrict
     T* dst = rb + (size_t)i * n23 + (size_t)j0 * N;
     if (D.vec) {
       constexpr int VW = 16 / sizeof(T);
-      constexpr int CH = N / VW;
+      constexpr int CH = N >= VW ? N / VW : 1;  // vector stores only for N * sizeof(T) >= 16
       for (int e = threadIdx.x; e < (nl >> 1) * CH; e += blockDim.x) {
         const int pr = e / CH, s0 = (e & (CH - 1)) * VW;
         VecT<T, VW> va, vb;
