@@ -93,6 +93,10 @@ typedef struct {
                           delta, rule, max_iter and the loads are taken from this call.  The
                           stopping iterate is stepped again, so a solve stopped by max_iter
                           and resumed follows the uninterrupted sequence bit for bit. */
+  int32_t record_history; /* nonzero: record, for each of the first max_iter iterations of
+                          every problem, (|e^k - xi^{k+1/2}|_{L2}, rho^k, energy of
+                          xi^{k+1/2}, |<v^k>|); read with ccmf_history.  Needs
+                          B * max_iter * 32 bytes of device memory.                   */
 } ccmf_options;
 
 /* Create a plan for n_fields crack-resistance fields of size dims[0] x dims[1] x
@@ -144,6 +148,14 @@ int ccmf_certificate(ccmf_plan p, double* cert, double* sigma);
  * the load xibar (not stated in the paper; it follows from that max-flow form), and
  * <xibar, mflux> -> geff.  mflux: host out, [B][3].  Errors: CCMF_ESTATE before a solve. */
 int ccmf_mean_flux(ccmf_plan p, double* mflux);
+
+/* Convergence history of the last solve (options.record_history set): out, host
+ * [B][max_len][4] with rows (residual, rho^k, energy, |<v^k>|) per iteration of the
+ * solve (the quantities of eq:convergence_criterion and the penalty of Sec. 3.2);
+ * rows at or beyond a problem's iteration count are NaN.  max_len >= 1; only the
+ * first min(max_len, max_iter) rows are recorded.
+ * Errors: CCMF_ESTATE when the last solve recorded no history. */
+int ccmf_history(ccmf_plan p, int32_t max_len, double* out);
 
 /* Checkpoint of the ADMM state of eq:CCMF_FFT_ADMM for every problem: the multiplier
  * v^k and e^k of the state the last solve stopped at (or the one set by ccmf_set_state),

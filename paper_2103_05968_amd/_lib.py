@@ -20,7 +20,7 @@ CCMF_F32 = 1
 RULES = {"bb": 0, "const": 1, "ltd": 2}
 
 EXPORTS = ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_certificate", "ccmf_mean_flux", "ccmf_get_state",
-           "ccmf_set_state", "ccmf_kernel_times", "ccmf_laplace_pinv", "ccmf_hartley_axis", "ccmf_stream_copy",
+           "ccmf_set_state", "ccmf_history", "ccmf_kernel_times", "ccmf_laplace_pinv", "ccmf_hartley_axis", "ccmf_stream_copy",
            "ccmf_destroy", "ccmf_last_error")
 
 
@@ -29,7 +29,8 @@ class Options(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("time_kernels", ctypes.c_int32), ("bb_min_corr", ctypes.c_double),
                 ("eta0", ctypes.c_double), ("k0", ctypes.c_double), ("eager", ctypes.c_int32),
-                ("no_autotune", ctypes.c_int32), ("warm_start", ctypes.c_int32)]
+                ("no_autotune", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("record_history", ctypes.c_int32)]
 
 
 class CcmfError(RuntimeError):
@@ -59,6 +60,7 @@ def load():
     lib.ccmf_mean_flux.argtypes = [vp, pd]
     lib.ccmf_get_state.argtypes = [vp, vp, vp, pd, pi32]
     lib.ccmf_set_state.argtypes = [vp, i64, vp, vp, pd, pi32]
+    lib.ccmf_history.argtypes = [vp, i32, pd]
     lib.ccmf_laplace_pinv.argtypes = [vp, vp, vp, i64]
     lib.ccmf_hartley_axis.argtypes = [vp, vp, i64, i32]
     lib.ccmf_stream_copy.argtypes = [vp, vp, i64, vp]
@@ -66,7 +68,7 @@ def load():
     lib.ccmf_destroy.restype = None
     lib.ccmf_last_error.restype = ctypes.c_char_p
     for name in ("ccmf_setup", "ccmf_solve", "ccmf_grad_kappa", "ccmf_certificate", "ccmf_mean_flux",
-                 "ccmf_get_state", "ccmf_set_state", "ccmf_kernel_times", "ccmf_laplace_pinv",
+                 "ccmf_get_state", "ccmf_set_state", "ccmf_history", "ccmf_kernel_times", "ccmf_laplace_pinv",
                  "ccmf_hartley_axis", "ccmf_stream_copy"):
         getattr(lib, name).restype = i32
     _lib = lib

@@ -29,6 +29,7 @@ class SolveResult:
     dual_est: np.ndarray        # [F, L] <A xibar, v^k>
     converged: bool
     mean_flux: np.ndarray = None          # [F, L, 3] <A* v^k>: d geff / d xibar at the optimum
+    history: Optional[np.ndarray] = None  # [F, L, I, 4] residual, rho, energy, |<v>| per iteration
     phi: Optional[torch.Tensor] = None    # [F, L, N1, N2, N3], float64
     flux: Optional[torch.Tensor] = None   # [F, L, 3, N1, N2, N3]
 
@@ -89,14 +90,15 @@ class Plan:
               want_phi: bool = False, want_flux: bool = False, time_kernels: bool = False,
               raise_not_converged: bool = False, bb_min_corr: float = 0.0, eta0: float = 0.0,
               k0: float = 0.0, eager: bool = False, autotune: bool = True,
-              warm_start: bool = False) -> SolveResult:
+              warm_start: bool = False, record_history: bool = False) -> SolveResult:
         xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(-1, 3))
         L = xi.shape[0]
         B = self.n_fields * L
         opt = _lib.Options(delta=delta, rho0=rho0, rule=_lib.RULES[rule], max_iter=max_iter,
                            check_every=check_every, time_kernels=int(bool(time_kernels)),
                            bb_min_corr=bb_min_corr, eta0=eta0, k0=k0, eager=int(bool(eager)),
-                           no_autotune=int(not autotune), warm_start=int(bool(warm_start)))
+                           no_autotune=int(not autotune), warm_start=int(bool(warm_start)),
+                           record_history=int(bool(record_history)))
         geff = np.zeros(B)
         iters = np.zeros(B, dtype=np.int32)
         res = np.zeros(B)
@@ -118,8 +120,14 @@ class Plan:
         shape = (self.n_fields, L)
         mflux = np.zeros((B, 3))
         _lib.check(self._lib.ccmf_mean_flux(self._h, mflux.ctypes.data_as(dp)))
+        hist = None
+        if record_history:
+            n = int(iters.max())
+            hist = np.zeros((B, n, 4))
+            _lib.check(self._lib.ccmf_history(self._h, n, hist.ctypes.data_as(dp)))
+            hist = hist.reshape(shape + (n, 4))
         return SolveResult(geff.reshape(shape), iters.reshape(shape), res.reshape(shape),
-                           dual.reshape(shape), code == _lib.CCMF_OK, mflux.reshape(shape + (3,)), phi, flux)
+                           dual.reshape(shape), code == _lib.CCMF_OK, mflux.reshape(shape + (3,)), hist, phi, flux)
 
     def get_state(self):
         """(v, e, rho, k) of the plan's state: v, e [F, L, 6, N1, N2, N3] in the plan's dtype."""

@@ -108,10 +108,12 @@ struct ccmf_plan_s {
   void* r = nullptr;       // r = div^- A* w in the plan dtype (aliases phi in FP64 mode)
   double* phi = nullptr;   // node potential, FP64 in both modes
   double* partials = nullptr;
-  int nparts = 0;
   Prob* prob = nullptr;    // device
   Prob* probh = nullptr;   // pinned host
   bool solved = false;
+  double* hist = nullptr;    // [B][hist_len][4] convergence history (record_history)
+  int hist_len = 0;
+  bool hist_valid = false;
   bool state_ready = false;  // z[.]/a[.] and probh hold a state a warm start can resume
   int upd_blocks = 0;        // blocks per problem of the stencil kernels (k_div, k_update)
   int tiles_per_blk = 0, tpp = 0;  // tile walk of the stencil kernels (see tile_of)
@@ -127,6 +129,7 @@ struct ccmf_plan_s {
   // captured chunk of iterations (HIP graph), valid for the current state buffers
   hipGraphExec_t gexec = nullptr;
   int graph_iters = 0;
+  const double* graph_hist = nullptr;  // history buffer baked into the captured graph
   Prob* flagsh[2] = {nullptr, nullptr};  // pinned copies of the scalars, one per chunk in flight
   hipEvent_t fev[2] = {nullptr, nullptr};
 
@@ -155,6 +158,7 @@ struct ccmf_plan_s {
     if (gexec) hipGraphExecDestroy(gexec);
     gexec = nullptr;
     graph_iters = 0;
+    graph_hist = nullptr;
   }
   void free_state() {
     drop_graph();
@@ -172,6 +176,10 @@ struct ccmf_plan_s {
     r = nullptr;
     phi = nullptr;
     hipFree(partials);
+    hipFree(hist);
+    hist = nullptr;
+    hist_len = 0;
+    hist_valid = false;
     hipFree(prob);
     if (probh) hipHostFree(probh);
     r = nullptr;
@@ -650,7 +658,8 @@ int run_iteration(ccmf_plan_s* p, int it, bool timed) {
   HIP_LAUNCH_CHECK();
   if (timed && (rc = record_event(p, &e1))) return rc;
   hipLaunchKernelGGL(k_finish, dim3((unsigned)p->B), dim3(kFinishThreads), 0, p->stream, p->N, p->upd_blocks,
-                     p->partials, p->prob, (double*)nullptr, 0);
+                     p->partials, p->prob, p->hist_valid ? p->hist : (double*)nullptr,
+                     p->hist_valid ? p->hist_len : 0);
   HIP_LAUNCH_CHECK();
   return CCMF_OK;
 }
@@ -793,6 +802,17 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
   if (rc) return rc;
   p->solved = false;
   p->state_ready = false;
+  p->hist_valid = false;
+  if (opt.record_history) {
+    if (p->hist == nullptr || p->hist_len != opt.max_iter) {
+      hipFree(p->hist);
+      p->hist = nullptr;
+      p->hist_len = 0;
+      HIP_TRY(hipMalloc(&p->hist, (size_t)p->B * opt.max_iter * 4 * sizeof(double)));
+      p->hist_len = opt.max_iter;
+    }
+    p->hist_valid = true;
+  }
 
   for (int64_t b = 0; b < p->B; ++b) {
     const int64_t f = b / nloads, l = b % nloads;
@@ -876,7 +896,8 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
     // index from the device and finished problems return at once.  The host
     // keeps one chunk in flight and inspects the flags of the previous one.
     const int K = (opt.check_every + 1) & ~1;
-    if (!p->gexec || p->graph_iters != K) {
+    const double* hist_now = p->hist_valid ? p->hist : nullptr;
+    if (!p->gexec || p->graph_iters != K || p->graph_hist != hist_now) {
       p->drop_graph();
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
@@ -895,6 +916,7 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
         return fail(CCMF_EDEVICE, "graph instantiate: %s", hipGetErrorString(ce));
       }
       p->graph_iters = K;
+      p->graph_hist = hist_now;
     }
     const int chunks = (opt.max_iter + K - 1) / K;
     for (int c = 0; c < chunks; ++c) {
@@ -1119,6 +1141,23 @@ int ccmf_mean_flux(ccmf_plan p, double* mflux) {
   if (!p->solved) return fail(CCMF_ESTATE, "ccmf_mean_flux needs a preceding ccmf_solve");
   for (int64_t b = 0; b < p->B; ++b)
     for (int c = 0; c < 3; ++c) mflux[3 * b + c] = p->probh[b].mflux[c];
+  return CCMF_OK;
+}
+
+int ccmf_history(ccmf_plan p, int32_t max_len, double* out) {
+  if (!p || !out || max_len < 1) return fail(CCMF_EINVAL, "bad argument");
+  if (!p->solved || !p->hist_valid) return fail(CCMF_ESTATE, "the last solve recorded no history");
+  const int rows = std::min<int>(max_len, p->hist_len);
+  std::vector<double> h((size_t)p->B * p->hist_len * 4);
+  HIP_TRY(hipMemcpyAsync(h.data(), p->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (int64_t b = 0; b < p->B; ++b) {
+    const int n = p->probh[b].k + 1;  // iterations taken by problem b
+    for (int i = 0; i < max_len; ++i)
+      for (int q = 0; q < 4; ++q)
+        out[((size_t)b * max_len + i) * 4 + q] =
+            (i < rows && i < n) ? h[((size_t)b * p->hist_len + i) * 4 + q] : std::nan("");
+  }
   return CCMF_OK;
 }
 

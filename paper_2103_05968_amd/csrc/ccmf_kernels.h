@@ -565,7 +565,7 @@ k_kappa_stats(const T* __restrict__ kap, uint32_t N, double* __restrict__ out) {
   s[2][threadIdx.x] = bad;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
       s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + w]);
       s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + w]);
       s[2][threadIdx.x] += s[2][threadIdx.x + w];
@@ -656,7 +656,7 @@ k_cert_sigma(Geo g, const T* __restrict__ kap, const T* __restrict__ z0, const T
   red[2][threadIdx.x] = ynorm;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
     }

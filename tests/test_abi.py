@@ -57,3 +57,4 @@ def test_error_paths_without_device():
                               ctypes.byref(k)) == _lib.CCMF_EINVAL
     assert lib.ccmf_laplace_pinv(None, ctypes.c_void_p(1), ctypes.c_void_p(1), 1) == _lib.CCMF_EINVAL
     assert lib.ccmf_kernel_times(None, None, None, None) == _lib.CCMF_EINVAL
+    assert lib.ccmf_history(None, 1, ctypes.byref(d)) == _lib.CCMF_EINVAL

@@ -194,3 +194,29 @@ def test_timed_solve_matches_untimed(eager):
     # one timed launch per iteration (graph replays run whole chunks of 32)
     assert count >= int(r.iterations.max()) and avg > 0.0
     assert per_problem == (15 * 4 + 8) * g.size
+
+
+# --- convergence history ------------------------------------------------------------
+
+@pytest.mark.parametrize("eager", [False, True])
+def test_history_matches_oracle(eager):
+    banner(f"history eager={eager}")
+    g = spheres((24, 20, 18))
+    K = 45
+    res = plan_of(g).solve([XB, (1, 0, 0)], tol=1e-300, max_iter=K, eager=eager, record_history=True)
+    assert res.history.shape == (1, 2, K, 4)
+    for l, xb in enumerate((XB, (1, 0, 0))):
+        ora = O.admm_solve(g, xb, tol=1e-300, max_iter=K, record=True)
+        h = np.array([[r, rho, e] for (_, r, rho, e) in ora.history])
+        got = res.history[0, l, :, :3]
+        assert np.all(np.abs(got - h).max(axis=0) <= np.abs(h).max(axis=0) * 1e-9), l
+    # a converged problem's rows stop at its iteration count
+    r2 = plan_of(np.full((8, 8, 8), 2.0)).solve([(1, 0, 0)], tol=1e-6, max_iter=50, record_history=True)
+    assert r2.iterations[0, 0] == 1 and r2.history.shape[2] == 1 and r2.history[0, 0, 0, 0] <= 1e-14
+    # a solve without recording has no history
+    import ctypes
+    from paper_2103_05968_amd import _lib
+    p = plan_of(g)
+    p.solve([XB], tol=1e-300, max_iter=3)
+    out = np.zeros(4)
+    assert p._lib.ccmf_history(p._h, 1, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == _lib.CCMF_ESTATE
