@@ -125,7 +125,7 @@ def main():
     ap.add_argument("--max-iter", type=int, default=60000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the solver on a single MI355X; "
+        print("bench.py measures one GPU: the solver runs on a single MI355X; "
               "multi-GPU runs (--gpus > 1) are not supported.", file=sys.stderr)
         raise SystemExit(2)
 
