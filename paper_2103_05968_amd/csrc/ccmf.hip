@@ -344,16 +344,20 @@ int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, 
 }
 
 // Plan variant of a pass.  The variant changes the radix decomposition, hence
-// the rounding, so it is a fixed function of the pass (never timed): results are
-// reproducible and a batched solve equals the single solves bit for bit.  From
-// the measured 256-point passes on MI355X: FP32 lines radix-16 (variant 0), FP64
-// lines radix-8/4 (variant 1), the fused divergence pass radix-4 (variant 2).
-// The diagnostic environment variable CCMF_FFT_VARIANT (0, 1 or 2) overrides it.
-int variant_of(int kind, bool fp64) {
+// the rounding, so it is a fixed function of the pass and the line length (never
+// timed): results are reproducible and a batched solve equals the single solves
+// bit for bit.  Chosen from per-pass timings of every variant on MI355X at 128,
+// 256 and 512 points: FP64 lines radix-8/4 (variant 1) up to 256 and radix-8 (0)
+// from 512; FP32 lines radix-8/4 below 256 and radix-16/8 (0) from 256; the
+// fused divergence pass radix-4 (2) in FP32 up to 256, else radix-8 (0), and in
+// FP64 radix-8 (0) up to 256, radix-16 (1) from 512.  The diagnostic environment
+// variable CCMF_FFT_VARIANT (0, 1 or 2) overrides it.
+int variant_of(int kind, bool fp64, int n) {
   const char* env = std::getenv("CCMF_FFT_VARIANT");
   if (env != nullptr && env[0] >= '0' && env[0] <= '2' && env[1] == '\0') return env[0] - '0';
-  if (kind == 5) return 2;
-  return fp64 ? 1 : 0;
+  if (kind == 5) return fp64 ? (n >= 512 ? 1 : 0) : (n >= 512 ? 0 : 2);
+  if (fp64) return n >= 512 ? 0 : 1;
+  return n >= 256 ? 0 : 1;
 }
 
 template <typename TI, typename TO, typename TC, int N>
@@ -361,7 +365,7 @@ int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, i
               bool middle, void* const* tws, const TC* s1, const TC* s2, const TC* s3, const Prob* prob,
               int kind) {
   // tws: the stage-major twiddle tables of the three plan variants for this precision
-  const int var = variant_of(kind, sizeof(TC) == 8);
+  const int var = variant_of(kind, sizeof(TC) == 8, N);
   if (var == 1)
     return launch_p2v<TI, TO, TC, N, 1>(p, in, out, count, A, outers, contig, middle, tws[1], s1, s2, s3, prob, kind);
   if (var == 2)
@@ -488,7 +492,7 @@ int launch_div_p2v(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, 
 
 template <typename T, int N>
 int launch_div_p2(ccmf_plan_s* p, const T* z, const T* a, T* r, int64_t count, const Prob* prob) {
-  const int var = variant_of(5, sizeof(T) == 8);
+  const int var = variant_of(5, sizeof(T) == 8, N);
   if (var == 1) return launch_div_p2v<T, N, 1>(p, z, a, r, count, prob);
   if (var == 2) return launch_div_p2v<T, N, 2>(p, z, a, r, count, prob);
   return launch_div_p2v<T, N, 0>(p, z, a, r, count, prob);
