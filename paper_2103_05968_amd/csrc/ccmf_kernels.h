@@ -230,22 +230,64 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
 #pragma unroll
   for (int q = 0; q < kNQU; ++q) acc[q] = 0.0;
 
+  // Plane walk (g.tpp > 0): step m+1 visits the same in-plane tile one i-plane
+  // further, so the x+e_1 values a thread loads at step m are its centre values
+  // at step m+1, and its centre values at step m are its x-e_1 values at step
+  // m+1.  They are carried in registers instead of being read again.
+  const bool walk = g.tpp > 0;
+  bool have = false;
+  T nx_a = T(0), nx_z3 = T(0), pv_a = T(0), pv_z0 = T(0);
+  double nx_ph = 0.0, pv_ph = 0.0;
+
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   for (int m = 0; m < g.tiles_per_blk; ++m) {
     const int t = tile_of(g, lb, m);
     if (t >= g.tiles) break;
     const uint32_t x = (uint32_t)t * kUpd + threadIdx.x;
-    if (x >= g.N) continue;
+    if (x >= g.N) {
+      have = false;
+      continue;
+    }
     const Nbr nb = neighbours(g, x);
-    const T al = ab[x];
-    const T bx = beta_of(al, irp, ir);
-    const double ph = pb[x];
-    const T gm = gam[x];
     T zo[6], xh[6];
+    T al, am0, z0m0;
+    double ph, phm0;
+    if (have) {
+      al = nx_a;
+      ph = nx_ph;
+      zo[3] = nx_z3;
+      am0 = pv_a;
+      z0m0 = pv_z0;
+      phm0 = pv_ph;
+    } else {
+      al = ab[x];
+      ph = pb[x];
+      zo[3] = zb[(size_t)3 * g.N + x];
+      am0 = ab[nb.m[0]];
+      z0m0 = zb[nb.m[0]];
+      phm0 = pb[nb.m[0]];
+    }
+    const T bx = beta_of(al, irp, ir);
+    const T gm = gam[x];
+    zo[0] = zb[x];
+    zo[1] = zb[(size_t)g.N + x];
+    zo[2] = zb[(size_t)2 * g.N + x];
+    zo[4] = zb[(size_t)4 * g.N + x];
+    zo[5] = zb[(size_t)5 * g.N + x];
+    const T ap0 = ab[nb.p[0]];
+    const T z3p0 = zb[(size_t)3 * g.N + nb.p[0]];
+    const double php0 = pb[nb.p[0]];
+    {
+      // c = 0 from the carried or freshly read x +- e_1 values
+      const T w2p = beta_of(ap0, irp, ir) * z3p0;
+      const T w1m = beta_of(am0, irp, ir) * z0m0;
+      const T tp = T(P.xibar[0] + (php0 - ph));
+      const T tm = T(P.xibar[0] + (ph - phm0));
+      xh[0] = tp * s + T(0.5) * (bx * zo[0] - w2p);
+      xh[3] = tm * s + T(0.5) * (bx * zo[3] - w1m);
+    }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) zo[q] = zb[(size_t)q * g.N + x];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 1; c < 3; ++c) {
       const T w2p = beta_of(ab[nb.p[c]], irp, ir) * zb[(size_t)(c + 3) * g.N + nb.p[c]];
       const T w1m = beta_of(ab[nb.m[c]], irp, ir) * zb[(size_t)c * g.N + nb.m[c]];
       // xibar + grad^+ phi formed in FP64: phi is O(N), its differences O(1)
@@ -254,6 +296,13 @@ k_update(Geo g, const T* __restrict__ kap, const T* __restrict__ z, const T* __r
       xh[c] = tp * s + T(0.5) * (bx * zo[c] - w2p);
       xh[c + 3] = tm * s + T(0.5) * (bx * zo[c + 3] - w1m);
     }
+    nx_a = ap0;
+    nx_z3 = z3p0;
+    nx_ph = php0;
+    pv_a = al;
+    pv_z0 = zo[0];
+    pv_ph = ph;
+    have = walk;
     const T ce = (T(1) - al) * irp;  // e^k = ce z, v^k = al z
     T d2 = T(0), xn2 = T(0), zn2 = T(0);
     T zz[6];
