@@ -122,6 +122,7 @@ struct ccmf_plan_s {
   // (0 forward k, 1 forward j, 2 fused i, 3 inverse j, 4 inverse k); 0 = rule of thumb
   // kind 5: r = div^- A* w fused with the forward k pass
   int nlc_hint[6] = {0, 0, 0, 0, 0, 0};
+  int walk_hint[5] = {0, 0, 0, 0, 0};     // tiles walked per block of passes 0-4; 0 = one
   int planes_hint = 0;                    // planes walked per block by the fused kernel
   int64_t tuned_B = 0;
   bool tuned_off = false;
@@ -322,7 +323,12 @@ int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, 
   if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) A.vec = 0;
   const size_t lds = (size_t)(nlc * LP + N) * 2 * sizeof(TC);
   if (lds > kMaxLds || nlc * TPL > 512) return fail(CCMF_EINVAL, "transform length %d too large for the LDS tile", N);
-  dim3 grid((unsigned)(outers * A.tiles_per_outer), (unsigned)count);
+  // tiles walked per block (the next tile's loads overlap the current transforms);
+  // the arithmetic of a tile does not depend on it
+  A.outers = outers;
+  A.walk = (kind >= 0 && kind < 5 && p->walk_hint[kind] > 0) ? p->walk_hint[kind] : 1;
+  const int ntiles = outers * A.tiles_per_outer;
+  dim3 grid((unsigned)((ntiles + A.walk - 1) / A.walk), (unsigned)count);
   dim3 block((unsigned)(nlc * TPL));
   const pow2::CX<TC>* tw = reinterpret_cast<const pow2::CX<TC>*>(twp);
   int rc;
@@ -702,6 +708,7 @@ int autotune(ccmf_plan_s* p) {
       for (int k = 0; k < 6; ++k) {
         p->nlc_hint[k] = it->second[k];
       }
+      for (int k = 0; k < 5; ++k) p->walk_hint[k] = it->second[6 + k];
       p->planes_hint = it->second[12];
       p->tuned_B = p->B;
       return CCMF_OK;
@@ -716,6 +723,7 @@ int autotune(ccmf_plan_s* p) {
   const bool log = std::getenv("CCMF_TUNE_LOG") != nullptr;  // per-candidate timings on stderr
   const bool present[6] = {p->n[2] > 1, p->n[1] > 1, true, p->n[1] > 1, p->n[2] > 1, fused_div_ok(p)};
   p->planes_hint = 0;
+  for (int k = 0; k < 5; ++k) p->walk_hint[k] = 0;
   for (int kind = 0; kind < 6; ++kind) {
     best[kind] = 0;
     if (!present[kind] || !is_pow2_len(p->ax[kind == 2 ? 0 : (kind == 1 || kind == 3) ? 1 : 2].n)) continue;
@@ -736,6 +744,27 @@ int autotune(ccmf_plan_s* p) {
       }
     }
     p->nlc_hint[kind] = best[kind];
+    // tiles walked per block at the chosen width
+    if (kind < 5 && best[kind] > 0) {
+      best[6 + kind] = 1;
+      for (int walk = 2; walk <= 8; walk <<= 1) {
+        p->walk_hint[kind] = walk;
+        if (run_pass<T>(p, kind) != CCMF_OK) break;
+        hipEventRecord(e0, p->stream);
+        for (int rep = 0; rep < 3; ++rep) run_pass<T>(p, kind);
+        hipEventRecord(e1, p->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) break;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (log) std::fprintf(stderr, "[ccmf tune] pass %d lines %d, %d tiles per block: %.1f us\n", kind,
+                              2 * best[kind], walk, ms / 3 * 1e3);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best[6 + kind] = walk;
+        }
+      }
+      p->walk_hint[kind] = best[6 + kind];
+    }
   }
   // planes walked per block by the fused divergence kernel
   best[12] = 0;
@@ -871,6 +900,7 @@ int solve_impl(ccmf_plan_s* p, const double* xi, int64_t nloads, double tol, con
     p->drop_graph();
     if (opt.no_autotune) {
       for (int k = 0; k < 6; ++k) p->nlc_hint[k] = 0;
+      for (int k = 0; k < 5; ++k) p->walk_hint[k] = 0;
       p->planes_hint = 0;
       p->tuned_B = p->B;
     } else if ((rc = autotune<T>(p))) {

@@ -63,6 +63,8 @@ struct DhtArgs {
   int32_t n2, n3;       // sizes of the other two axes (middle pass: line index = q3, outer = q2)
   int32_t lognl;        // log2(nl) for the power-of-two kernel
   int32_t vec;          // power-of-two kernel: vector loads/stores are aligned
+  int32_t outers;       // power-of-two kernel: number of outer indices
+  int32_t walk;         // power-of-two kernel: tiles walked per block
 };
 
 // forward DFT of radix R on registers, exp(-2 pi i p r / R)
@@ -363,6 +365,25 @@ struct alignas(sizeof(T) * V) VecT {
   T v[V];
 };
 
+// Input samples of one tile held in registers between the global loads and the
+// LDS tile, so that the loads of the next tile are in flight while the current
+// tile is transformed.  Rows (CONTIG): IT iterations of two VW-vectors (the two
+// rows of a pair); columns: IT iterations of one 2-vector (both lines of a pair
+// are adjacent in memory).
+template <typename TI, int N, int E, bool CONTIG>
+struct TileRegs {
+  static constexpr int VW = CONTIG ? 16 / (int)sizeof(TI) : 2;
+  static constexpr int TPL = N / E;
+  static constexpr int CH = N >= VW ? N / VW : 1;
+  static constexpr int IT = CONTIG ? (CH + TPL - 1) / TPL : E;
+  VecT<TI, VW> va[IT];
+  VecT<TI, VW> vb[CONTIG ? IT : 1];
+};
+
+// One Hartley pass over a tile of `nl` lines; MIDDLE additionally scales by
+// m(q) and transforms again along the same axis (see k_hartley).  A block walks
+// A.walk consecutive tiles (same outer index, adjacent lines), loading the next
+// tile's samples into registers before it transforms the current one.
 template <typename TI, typename TO, typename TC, int N, int V, bool CONTIG, bool MIDDLE>
 __global__ void __launch_bounds__(512)
 k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs A,
@@ -373,123 +394,160 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
   if (prob != nullptr && prob[b].done) return;
   using P = pow2::Plan<N, V>;
   constexpr int E = P::E, TPL = N / E, LP = line_pitch<N, V>();
+  using RG = TileRegs<TI, N, E, CONTIG>;
   const int nl = 1 << A.lognl;
   pow2::CX<TC>* L = reinterpret_cast<pow2::CX<TC>*>(smem_raw);
   TC* Lr = reinterpret_cast<TC*>(smem_raw);
   const int c = threadIdx.x / TPL, t = threadIdx.x & (TPL - 1);
-
-  // XCD-contiguous tiles: neighbouring tiles share the 128-byte lines of a row
-  const int bx = xcd_remap(blockIdx.x, gridDim.x);
-  const int outer = bx / A.tiles_per_outer;
-  const int lt = bx - outer * A.tiles_per_outer;
-  const int line0 = lt * nl;
-  const int nvalid = min(nl, A.lines_total - line0);
-  const size_t off = (size_t)b * A.field_stride + (size_t)outer * A.os + (size_t)line0 * A.ls;
-  const TI* src = in + off;
-  TO* dst = out + off;
   const int total = nl * N;
+  const TI* src_b = in + (size_t)b * A.field_stride;
+  TO* dst_b = out + (size_t)b * A.field_stride;
 
   // twiddle table of this length staged in LDS behind the data tile
   pow2::CX<TC>* twl = L + (size_t)(nl >> 1) * LP;
   for (int j = threadIdx.x; j < N; j += blockDim.x) twl[j] = tw[j];
 
-  if (A.vec) {
-    if constexpr (CONTIG) {
-      // rows: V consecutive samples of both rows of a pair per thread
-      constexpr int VW = 16 / sizeof(TI);
-      constexpr int CH = N >= VW ? N / VW : 1;  // the host enables vector IO only for N >= VW
-      for (int e = threadIdx.x; e < (nl >> 1) * CH; e += blockDim.x) {
-        const int pr = e / CH, s0 = (e & (CH - 1)) * VW;
-        VecT<TI, VW> va, vb;
-#pragma unroll
-        for (int v = 0; v < VW; ++v) va.v[v] = vb.v[v] = TI(0);
-        if (2 * pr < nvalid) va = *reinterpret_cast<const VecT<TI, VW>*>(src + (size_t)(2 * pr) * A.ls + s0);
-        if (2 * pr + 1 < nvalid) vb = *reinterpret_cast<const VecT<TI, VW>*>(src + (size_t)(2 * pr + 1) * A.ls + s0);
-#pragma unroll
-        for (int v = 0; v < VW; ++v) L[pr * LP + pidx<N, V>(s0 + v)] = {TC(va.v[v]), TC(vb.v[v])};
-      }
-    } else {
-      // columns: both lines of a pair are adjacent in memory
-      const int lognlc = A.lognl - 1;
-      for (int e = threadIdx.x; e < (nl >> 1) * N; e += blockDim.x) {
-        const int sp = e >> lognlc, pr = e & ((1 << lognlc) - 1);
-        VecT<TI, 2> v2;
-        v2.v[0] = v2.v[1] = TI(0);
-        if (2 * pr < nvalid) v2 = *reinterpret_cast<const VecT<TI, 2>*>(src + (size_t)sp * A.ss + 2 * pr);
-        L[pr * LP + pidx<N, V>(sp)] = {TC(v2.v[0]), TC(v2.v[1])};
-      }
-    }
-  } else {
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      int s, l;
-      tile_coords_p2<CONTIG, N>(e, A.lognl, s, l);
-      const TC v = (l < nvalid) ? TC(src[(size_t)s * A.ss + (size_t)l * A.ls]) : TC(0);
-      Lr[((l >> 1) * LP + pidx<N, V>(s)) * 2 + (l & 1)] = v;
-    }
-  }
-  __syncthreads();
-  fft_line_p2<TC, N, V>(L + c * LP, t, twl);
+  // XCD-contiguous tiles: neighbouring tiles share the 128-byte lines of a row
+  const int ntiles = A.outers * A.tiles_per_outer;
+  const int tile0 = xcd_remap(blockIdx.x, gridDim.x) * A.walk;
+  const int tile_end = min(tile0 + A.walk, ntiles);
 
-  if constexpr (MIDDLE) {
-    // Scale the Hartley coefficients by m(q) = 1/(lambda(q) N) and repack them
-    // as the next transform's input.  Positions s and N-s of a complex line hold
-    // both coefficients of its two real lines at s and N-s, and lambda(s) =
-    // lambda(N-s), so each thread rewrites its own pairs in place.
-    const int la = 2 * c, lb = 2 * c + 1;
-    const TC sa = (la < nvalid) ? s2[outer] + s3[line0 + la] : TC(-1);
-    const TC sb = (lb < nvalid) ? s2[outer] + s3[line0 + lb] : TC(-1);
-    pow2::CX<TC>* Lc = L + c * LP;
-    for (int sp = t; sp <= N / 2; sp += TPL) {
-      const int sm = (N - sp) & (N - 1);
-      const pow2::CX<TC> zs = Lc[pidx<N, V>(sp)], zm = Lc[pidx<N, V>(sm)];
-      const TC ha_s = TC(0.5) * ((zs.x + zm.x) - (zs.y - zm.y));
-      const TC hb_s = TC(0.5) * ((zs.y + zm.y) + (zs.x - zm.x));
-      const TC ha_m = TC(0.5) * ((zm.x + zs.x) - (zm.y - zs.y));
-      const TC hb_m = TC(0.5) * ((zm.y + zs.y) + (zm.x - zs.x));
-      const TC s1v = s1[sp];
-      const TC lam_a = s1v + sa, lam_b = s1v + sb;     // lambda(q) = -lam
-      const TC ma = (sa >= TC(0) && lam_a > TC(0)) ? -TC(A.scale) / lam_a : TC(0);
-      const TC mb = (sb >= TC(0) && lam_b > TC(0)) ? -TC(A.scale) / lam_b : TC(0);
-      Lc[pidx<N, V>(sp)] = {ha_s * ma, hb_s * mb};
-      Lc[pidx<N, V>(sm)] = {ha_m * ma, hb_m * mb};
+  auto tile_base = [&](int tile, int& outer, int& line0, int& nvalid) -> size_t {
+    outer = tile / A.tiles_per_outer;
+    line0 = (tile - outer * A.tiles_per_outer) * nl;
+    nvalid = min(nl, A.lines_total - line0);
+    return (size_t)outer * A.os + (size_t)line0 * A.ls;
+  };
+  // global -> registers (vector paths)
+  auto load_regs = [&](int tile, RG& R) {
+    int outer, line0, nvalid;
+    const TI* src = src_b + tile_base(tile, outer, line0, nvalid);
+#pragma unroll
+    for (int it = 0; it < RG::IT; ++it) {
+      const int e = threadIdx.x + it * (int)blockDim.x;
+      if constexpr (CONTIG) {
+        // e < (nl/2) CH except for plans with fewer than VW samples per thread
+        if (RG::IT * TPL == RG::CH || e < (nl >> 1) * RG::CH) {
+          const int pr = e / RG::CH, s0 = (e & (RG::CH - 1)) * RG::VW;
+          const int ra = min(2 * pr, nvalid - 1), rb = min(2 * pr + 1, nvalid - 1);
+          R.va[it] = *reinterpret_cast<const VecT<TI, RG::VW>*>(src + (size_t)ra * A.ls + s0);
+          R.vb[it] = *reinterpret_cast<const VecT<TI, RG::VW>*>(src + (size_t)rb * A.ls + s0);
+        }
+      } else {
+        // pairs are whole: n3 and nl are even, so nvalid is even
+        const int lognlc = A.lognl - 1;
+        const int sp = e >> lognlc, pr = min(e & ((1 << lognlc) - 1), (nvalid >> 1) - 1);
+        R.va[it] = *reinterpret_cast<const VecT<TI, 2>*>(src + (size_t)sp * A.ss + 2 * pr);
+      }
+    }
+  };
+  // registers -> LDS tile
+  auto put_regs = [&](const RG& R, int nvalid) {
+#pragma unroll
+    for (int it = 0; it < RG::IT; ++it) {
+      const int e = threadIdx.x + it * (int)blockDim.x;
+      if constexpr (CONTIG) {
+        if (RG::IT * TPL == RG::CH || e < (nl >> 1) * RG::CH) {
+          const int pr = e / RG::CH, s0 = (e & (RG::CH - 1)) * RG::VW;
+          const bool oka = 2 * pr < nvalid, okb = 2 * pr + 1 < nvalid;
+#pragma unroll
+          for (int v = 0; v < RG::VW; ++v)
+            L[pr * LP + pidx<N, V>(s0 + v)] = {oka ? TC(R.va[it].v[v]) : TC(0), okb ? TC(R.vb[it].v[v]) : TC(0)};
+        }
+      } else {
+        const int lognlc = A.lognl - 1;
+        const int sp = e >> lognlc, pr = e & ((1 << lognlc) - 1);
+        const bool ok = 2 * pr < nvalid;
+        L[pr * LP + pidx<N, V>(sp)] = {ok ? TC(R.va[it].v[0]) : TC(0), ok ? TC(R.va[it].v[1]) : TC(0)};
+      }
+    }
+  };
+
+  RG R;
+  if (A.vec && tile0 < tile_end) load_regs(tile0, R);
+  for (int tile = tile0; tile < tile_end; ++tile) {
+    int outer, line0, nvalid;
+    const size_t off = tile_base(tile, outer, line0, nvalid);
+    if (A.vec) {
+      put_regs(R, nvalid);
+    } else {
+      const TI* src = src_b + off;
+      for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int s, l;
+        tile_coords_p2<CONTIG, N>(e, A.lognl, s, l);
+        const TC v = (l < nvalid) ? TC(src[(size_t)s * A.ss + (size_t)l * A.ls]) : TC(0);
+        Lr[((l >> 1) * LP + pidx<N, V>(s)) * 2 + (l & 1)] = v;
+      }
     }
     __syncthreads();
+    // the next tile's loads overlap this tile's transforms
+    if (A.vec && tile + 1 < tile_end) load_regs(tile + 1, R);
     fft_line_p2<TC, N, V>(L + c * LP, t, twl);
-  }
 
-  if (A.vec) {
-    if constexpr (CONTIG) {
-      constexpr int VW = 16 / sizeof(TO);
-      constexpr int CH = N >= VW ? N / VW : 1;
-      for (int e = threadIdx.x; e < (nl >> 1) * CH; e += blockDim.x) {
-        const int pr = e / CH, s0 = (e & (CH - 1)) * VW;
-        VecT<TO, VW> va, vb;
+    if constexpr (MIDDLE) {
+      // Scale the Hartley coefficients by m(q) = 1/(lambda(q) N) and repack them
+      // as the next transform's input.  Positions s and N-s of a complex line hold
+      // both coefficients of its two real lines at s and N-s, and lambda(s) =
+      // lambda(N-s), so each thread rewrites its own pairs in place.
+      const int la = 2 * c, lb = 2 * c + 1;
+      const TC sa = (la < nvalid) ? s2[outer] + s3[line0 + la] : TC(-1);
+      const TC sb = (lb < nvalid) ? s2[outer] + s3[line0 + lb] : TC(-1);
+      pow2::CX<TC>* Lc = L + c * LP;
+      for (int sp = t; sp <= N / 2; sp += TPL) {
+        const int sm = (N - sp) & (N - 1);
+        const pow2::CX<TC> zs = Lc[pidx<N, V>(sp)], zm = Lc[pidx<N, V>(sm)];
+        const TC ha_s = TC(0.5) * ((zs.x + zm.x) - (zs.y - zm.y));
+        const TC hb_s = TC(0.5) * ((zs.y + zm.y) + (zs.x - zm.x));
+        const TC ha_m = TC(0.5) * ((zm.x + zs.x) - (zm.y - zs.y));
+        const TC hb_m = TC(0.5) * ((zm.y + zs.y) + (zm.x - zs.x));
+        const TC s1v = s1[sp];
+        const TC lam_a = s1v + sa, lam_b = s1v + sb;     // lambda(q) = -lam
+        const TC ma = (sa >= TC(0) && lam_a > TC(0)) ? -TC(A.scale) / lam_a : TC(0);
+        const TC mb = (sb >= TC(0) && lam_b > TC(0)) ? -TC(A.scale) / lam_b : TC(0);
+        Lc[pidx<N, V>(sp)] = {ha_s * ma, hb_s * mb};
+        Lc[pidx<N, V>(sm)] = {ha_m * ma, hb_m * mb};
+      }
+      __syncthreads();
+      fft_line_p2<TC, N, V>(L + c * LP, t, twl);
+    }
+
+    TO* dst = dst_b + off;
+    if (A.vec) {
+      if constexpr (CONTIG) {
+        constexpr int VW = 16 / sizeof(TO);
+        constexpr int CH = N >= VW ? N / VW : 1;
+        for (int e = threadIdx.x; e < (nl >> 1) * CH; e += blockDim.x) {
+          const int pr = e / CH, s0 = (e & (CH - 1)) * VW;
+          VecT<TO, VW> va, vb;
 #pragma unroll
-        for (int v = 0; v < VW; ++v) {
-          va.v[v] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr, s0 + v));
-          vb.v[v] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr + 1, s0 + v));
+          for (int v = 0; v < VW; ++v) {
+            va.v[v] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr, s0 + v));
+            vb.v[v] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr + 1, s0 + v));
+          }
+          if (2 * pr < nvalid) *reinterpret_cast<VecT<TO, VW>*>(dst + (size_t)(2 * pr) * A.ls + s0) = va;
+          if (2 * pr + 1 < nvalid) *reinterpret_cast<VecT<TO, VW>*>(dst + (size_t)(2 * pr + 1) * A.ls + s0) = vb;
         }
-        if (2 * pr < nvalid) *reinterpret_cast<VecT<TO, VW>*>(dst + (size_t)(2 * pr) * A.ls + s0) = va;
-        if (2 * pr + 1 < nvalid) *reinterpret_cast<VecT<TO, VW>*>(dst + (size_t)(2 * pr + 1) * A.ls + s0) = vb;
+      } else {
+        const int lognlc = A.lognl - 1;
+        for (int e = threadIdx.x; e < (nl >> 1) * N; e += blockDim.x) {
+          const int sp = e >> lognlc, pr = e & ((1 << lognlc) - 1);
+          if (2 * pr < nvalid) {
+            VecT<TO, 2> v2;
+            v2.v[0] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr, sp));
+            v2.v[1] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr + 1, sp));
+            *reinterpret_cast<VecT<TO, 2>*>(dst + (size_t)sp * A.ss + 2 * pr) = v2;
+          }
+        }
       }
     } else {
-      const int lognlc = A.lognl - 1;
-      for (int e = threadIdx.x; e < (nl >> 1) * N; e += blockDim.x) {
-        const int sp = e >> lognlc, pr = e & ((1 << lognlc) - 1);
-        if (2 * pr < nvalid) {
-          VecT<TO, 2> v2;
-          v2.v[0] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr, sp));
-          v2.v[1] = TO(hartley_p2<TC, N, V>(L, LP, 2 * pr + 1, sp));
-          *reinterpret_cast<VecT<TO, 2>*>(dst + (size_t)sp * A.ss + 2 * pr) = v2;
-        }
+      for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        int s, l;
+        tile_coords_p2<CONTIG, N>(e, A.lognl, s, l);
+        if (l < nvalid) dst[(size_t)s * A.ss + (size_t)l * A.ls] = TO(hartley_p2<TC, N, V>(L, LP, l, s));
       }
     }
-  } else {
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      int s, l;
-      tile_coords_p2<CONTIG, N>(e, A.lognl, s, l);
-      if (l < nvalid) dst[(size_t)s * A.ss + (size_t)l * A.ls] = TO(hartley_p2<TC, N, V>(L, LP, l, s));
-    }
+    // the tile is rewritten by the next iteration
+    __syncthreads();
   }
 }
 
@@ -541,12 +599,20 @@ k_div_hartley_p2(const T* __restrict__ z, const T* __restrict__ a, T* __restrict
     if (i >= D.n1) break;
     const uint32_t ip = (i + 1 == D.n1) ? 0u : (uint32_t)(i + 1);
     const uint32_t im = (i == 0) ? (uint32_t)(D.n1 - 1) : (uint32_t)(i - 1);
-    // r for the tile's rows, written into the LDS tile as real lines
-    for (int e = threadIdx.x; e < nl * N; e += blockDim.x) {
-      const int l = e / N, k = e & (N - 1);
-      T rv = T(0);
-      if (l < nvalid) {
-        const uint32_t j = (uint32_t)(j0 + l);
+    // r for the tile's rows, written into the LDS tile as real lines.  The loop
+    // has 2E trips (blockDim = nl N / (2E)); the samples of U elements are loaded
+    // first, branch-free (rows past the edge of the cell read row n2 - 1 and are
+    // zeroed afterwards), so that their loads are in flight together.
+    constexpr int ITS = 2 * E;
+    constexpr int U = sizeof(T) == 8 ? 2 : 4;
+    static_assert(ITS % U == 0, "trip count");
+    for (int g0 = 0; g0 < ITS; g0 += U) {
+      T zc[U][6], ac[U], ap[U][3], zp[U][3], am[U][3], zm[U][3];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = threadIdx.x + (g0 + u) * (int)blockDim.x;
+        const int l = e / N, k = e & (N - 1);
+        const uint32_t j = (uint32_t)min(j0 + l, D.n2 - 1);
         const uint32_t jp = (j + 1 == (uint32_t)D.n2) ? 0u : j + 1;
         const uint32_t jm = (j == 0) ? (uint32_t)(D.n2 - 1) : j - 1;
         const uint32_t kp = (k + 1 == N) ? 0u : (uint32_t)(k + 1);
@@ -555,19 +621,34 @@ k_div_hartley_p2(const T* __restrict__ z, const T* __restrict__ a, T* __restrict
         const uint32_t x = row + k;
         const uint32_t xp[3] = {ip * n23 + j * N + k, (uint32_t)i * n23 + jp * N + k, row + kp};
         const uint32_t xm[3] = {im * n23 + j * N + k, (uint32_t)i * n23 + jm * N + k, row + km};
-        const T bx0 = beta_of(ab[x], irp, ir);
+        ac[u] = ab[x];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) zc[u][q] = zb[(size_t)q * NN + x];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          ap[u][q] = ab[xp[q]];
+          zp[u][q] = zb[(size_t)(q + 3) * NN + xp[q]];
+          am[u][q] = ab[xm[q]];
+          zm[u][q] = zb[(size_t)q * NN + xm[q]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = threadIdx.x + (g0 + u) * (int)blockDim.x;
+        const int l = e / N, k = e & (N - 1);
+        const T bx0 = beta_of(ac[u], irp, ir);
         T acc = T(0);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const T w1 = bx0 * zb[(size_t)q * NN + x];
-          const T w2 = bx0 * zb[(size_t)(q + 3) * NN + x];
-          const T w2p = beta_of(ab[xp[q]], irp, ir) * zb[(size_t)(q + 3) * NN + xp[q]];
-          const T w1m = beta_of(ab[xm[q]], irp, ir) * zb[(size_t)q * NN + xm[q]];
+          const T w1 = bx0 * zc[u][q];
+          const T w2 = bx0 * zc[u][q + 3];
+          const T w2p = beta_of(ap[u][q], irp, ir) * zp[u][q];
+          const T w1m = beta_of(am[u][q], irp, ir) * zm[u][q];
           acc += (w1 + w2p) - (w1m + w2);
         }
-        rv = acc * T(0.70710678118654752440);
+        const T rv = (l < nvalid) ? acc * T(0.70710678118654752440) : T(0);
+        Lr[((l >> 1) * LP + pidx<N, V>(k)) * 2 + (l & 1)] = rv;
       }
-      Lr[((l >> 1) * LP + pidx<N, V>(k)) * 2 + (l & 1)] = rv;
     }
     __syncthreads();
     fft_line_p2<T, N, V>(L + c * LP, t, twl);
