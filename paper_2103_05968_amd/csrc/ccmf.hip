@@ -299,14 +299,17 @@ int allow_lds(const void* kernel, size_t lds) {
 
 template <typename TI, typename TO, typename TC, int N, int V>
 int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
-               bool middle, const void* twp, const TC* s1, const TC* s2, const TC* s3, const Prob* prob, int kind) {
+               bool middle, const void* twp, const void* twp32, const TC* s1, const TC* s2, const TC* s3,
+               const Prob* prob, int kind) {
   constexpr int E = pow2::Plan<N, V>::E, TPL = N / E;
   constexpr int LP = line_pitch<N, V>();
+  // the middle pass of FP32 fields also stages the FP32 twiddles of its forward transform
+  const size_t tw32_bytes = (middle && sizeof(TI) == 4 && sizeof(TC) == 8) ? (size_t)N * 2 * sizeof(float) : 0;
   int nlc = 16;
   if (kind >= 0 && p->nlc_hint[kind] > 0) {
     nlc = p->nlc_hint[kind];
   } else {
-    while (nlc > 1 && (nlc * TPL > 512 || (size_t)(nlc * LP + N) * 2 * sizeof(TC) > 65536)) nlc >>= 1;
+    while (nlc > 1 && (nlc * TPL > 512 || (size_t)(nlc * LP + N) * 2 * sizeof(TC) + tw32_bytes > 65536)) nlc >>= 1;
     while (nlc > 1 && 2 * (nlc >> 1) >= A.lines_total) nlc >>= 1;  // do not pad tiny line counts
   }
   const int nl = 2 * nlc;
@@ -321,7 +324,7 @@ int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, 
   else
     A.vec = (p->n[2] % 2 == 0) ? 1 : 0;
   if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) A.vec = 0;
-  const size_t lds = (size_t)(nlc * LP + N) * 2 * sizeof(TC);
+  const size_t lds = (size_t)(nlc * LP + N) * 2 * sizeof(TC) + tw32_bytes;
   if (lds > kMaxLds || nlc * TPL > 512) return fail(CCMF_EINVAL, "transform length %d too large for the LDS tile", N);
   // tiles walked per block (the next tile's loads overlap the current transforms);
   // the arithmetic of a tile does not depend on it
@@ -331,19 +334,20 @@ int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, 
   dim3 grid((unsigned)((ntiles + A.walk - 1) / A.walk), (unsigned)count);
   dim3 block((unsigned)(nlc * TPL));
   const pow2::CX<TC>* tw = reinterpret_cast<const pow2::CX<TC>*>(twp);
+  const pow2::CX<float>* tw32 = reinterpret_cast<const pow2::CX<float>*>(twp32);
   int rc;
   if (middle) {
     if ((rc = allow_lds((const void*)k_hartley_p2<TI, TO, TC, N, V, false, true>, lds))) return rc;
-    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, false, true>), grid, block, lds, p->stream, in, out, tw, A, s1,
-                       s2, s3, prob);
+    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, false, true>), grid, block, lds, p->stream, in, out, tw, tw32,
+                       A, s1, s2, s3, prob);
   } else if (contig) {
     if ((rc = allow_lds((const void*)k_hartley_p2<TI, TO, TC, N, V, true, false>, lds))) return rc;
-    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, true, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
-                       s2, s3, prob);
+    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, true, false>), grid, block, lds, p->stream, in, out, tw, tw32,
+                       A, s1, s2, s3, prob);
   } else {
     if ((rc = allow_lds((const void*)k_hartley_p2<TI, TO, TC, N, V, false, false>, lds))) return rc;
-    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, false, false>), grid, block, lds, p->stream, in, out, tw, A, s1,
-                       s2, s3, prob);
+    hipLaunchKernelGGL((k_hartley_p2<TI, TO, TC, N, V, false, false>), grid, block, lds, p->stream, in, out, tw, tw32,
+                       A, s1, s2, s3, prob);
   }
   HIP_LAUNCH_CHECK();
   return CCMF_OK;
@@ -368,15 +372,19 @@ int variant_of(int kind, bool fp64, int n) {
 
 template <typename TI, typename TO, typename TC, int N>
 int launch_p2(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, int outers, bool contig,
-              bool middle, void* const* tws, const TC* s1, const TC* s2, const TC* s3, const Prob* prob,
-              int kind) {
-  // tws: the stage-major twiddle tables of the three plan variants for this precision
+              bool middle, void* const* tws, void* const* tws32, const TC* s1, const TC* s2, const TC* s3,
+              const Prob* prob, int kind) {
+  // tws, tws32: the stage-major twiddle tables of the three plan variants in the
+  // compute precision and in FP32
   const int var = variant_of(kind, sizeof(TC) == 8, N);
   if (var == 1)
-    return launch_p2v<TI, TO, TC, N, 1>(p, in, out, count, A, outers, contig, middle, tws[1], s1, s2, s3, prob, kind);
+    return launch_p2v<TI, TO, TC, N, 1>(p, in, out, count, A, outers, contig, middle, tws[1], tws32[1], s1, s2, s3,
+                                        prob, kind);
   if (var == 2)
-    return launch_p2v<TI, TO, TC, N, 2>(p, in, out, count, A, outers, contig, middle, tws[2], s1, s2, s3, prob, kind);
-  return launch_p2v<TI, TO, TC, N, 0>(p, in, out, count, A, outers, contig, middle, tws[0], s1, s2, s3, prob, kind);
+    return launch_p2v<TI, TO, TC, N, 2>(p, in, out, count, A, outers, contig, middle, tws[2], tws32[2], s1, s2, s3,
+                                        prob, kind);
+  return launch_p2v<TI, TO, TC, N, 0>(p, in, out, count, A, outers, contig, middle, tws[0], tws32[0], s1, s2, s3,
+                                      prob, kind);
 }
 
 // Launch one Hartley pass along `axis` over `count` fields: load TI from `in`,
@@ -426,17 +434,17 @@ int launch_hartley(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, int axi
   const TC* s3 = reinterpret_cast<const TC*>(p->ax[2].s[q]);
   if (is_pow2_len(A.n)) {
     switch (A.n) {
-      case 2: return launch_p2<TI, TO, TC, 2>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 4: return launch_p2<TI, TO, TC, 4>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 8: return launch_p2<TI, TO, TC, 8>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 16: return launch_p2<TI, TO, TC, 16>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 32: return launch_p2<TI, TO, TC, 32>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 64: return launch_p2<TI, TO, TC, 64>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 128: return launch_p2<TI, TO, TC, 128>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 256: return launch_p2<TI, TO, TC, 256>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 512: return launch_p2<TI, TO, TC, 512>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 1024: return launch_p2<TI, TO, TC, 1024>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
-      case 2048: return launch_p2<TI, TO, TC, 2048>(p, in, out, count, A, outers, contig, middle, ax.tws[q], s1, s2, s3, prob, kind);
+      case 2: return launch_p2<TI, TO, TC, 2>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 4: return launch_p2<TI, TO, TC, 4>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 8: return launch_p2<TI, TO, TC, 8>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 16: return launch_p2<TI, TO, TC, 16>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 32: return launch_p2<TI, TO, TC, 32>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 64: return launch_p2<TI, TO, TC, 64>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 128: return launch_p2<TI, TO, TC, 128>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 256: return launch_p2<TI, TO, TC, 256>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 512: return launch_p2<TI, TO, TC, 512>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 1024: return launch_p2<TI, TO, TC, 1024>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
+      case 2048: return launch_p2<TI, TO, TC, 2048>(p, in, out, count, A, outers, contig, middle, ax.tws[q], ax.tws[prec_index<float>()], s1, s2, s3, prob, kind);
       default: break;
     }
   }

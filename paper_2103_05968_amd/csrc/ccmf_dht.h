@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ccmf_fft_pow2.h"
 #include "ccmf_kernels.h"
 
@@ -384,10 +386,14 @@ struct TileRegs {
 // m(q) and transforms again along the same axis (see k_hartley).  A block walks
 // A.walk consecutive tiles (same outer index, adjacent lines), loading the next
 // tile's samples into registers before it transforms the current one.
+// With FP32 samples and FP64 compute (the middle pass of FP32 fields) the
+// forward transform runs in FP32 like the other forward passes (tw32: its
+// twiddles) and the coefficients are widened to FP64 before the scaling, so
+// the inverse transform and the potential are FP64.
 template <typename TI, typename TO, typename TC, int N, int V, bool CONTIG, bool MIDDLE>
 __global__ void __launch_bounds__(512)
-k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs A,
-             const TC* __restrict__ s1, const TC* __restrict__ s2, const TC* __restrict__ s3,
+k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, const pow2::CX<float>* __restrict__ tw32,
+             DhtArgs A, const TC* __restrict__ s1, const TC* __restrict__ s2, const TC* __restrict__ s3,
              const Prob* __restrict__ prob) {
   extern __shared__ unsigned char smem_raw[];
   const int b = blockIdx.y;
@@ -395,17 +401,26 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
   using P = pow2::Plan<N, V>;
   constexpr int E = P::E, TPL = N / E, LP = line_pitch<N, V>();
   using RG = TileRegs<TI, N, E, CONTIG>;
+  constexpr bool F32FWD = MIDDLE && sizeof(TI) == 4 && sizeof(TC) == 8;
+  using TF = typename std::conditional<F32FWD, float, TC>::type;  // forward transform type
   const int nl = 1 << A.lognl;
   pow2::CX<TC>* L = reinterpret_cast<pow2::CX<TC>*>(smem_raw);
-  TC* Lr = reinterpret_cast<TC*>(smem_raw);
+  pow2::CX<TF>* LF = reinterpret_cast<pow2::CX<TF>*>(smem_raw);  // same tile, forward type
+  TF* LFr = reinterpret_cast<TF*>(smem_raw);
   const int c = threadIdx.x / TPL, t = threadIdx.x & (TPL - 1);
   const int total = nl * N;
   const TI* src_b = in + (size_t)b * A.field_stride;
   TO* dst_b = out + (size_t)b * A.field_stride;
 
-  // twiddle table of this length staged in LDS behind the data tile
+  // twiddle table of this length staged in LDS behind the data tile (and the
+  // FP32 table of the forward transform behind it)
   pow2::CX<TC>* twl = L + (size_t)(nl >> 1) * LP;
   for (int j = threadIdx.x; j < N; j += blockDim.x) twl[j] = tw[j];
+  pow2::CX<TF>* twf = reinterpret_cast<pow2::CX<TF>*>(twl);
+  if constexpr (F32FWD) {
+    twf = reinterpret_cast<pow2::CX<TF>*>(twl + N);
+    for (int j = threadIdx.x; j < N; j += blockDim.x) twf[j] = tw32[j];
+  }
 
   // XCD-contiguous tiles: neighbouring tiles share the 128-byte lines of a row
   const int ntiles = A.outers * A.tiles_per_outer;
@@ -452,13 +467,13 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
           const bool oka = 2 * pr < nvalid, okb = 2 * pr + 1 < nvalid;
 #pragma unroll
           for (int v = 0; v < RG::VW; ++v)
-            L[pr * LP + pidx<N, V>(s0 + v)] = {oka ? TC(R.va[it].v[v]) : TC(0), okb ? TC(R.vb[it].v[v]) : TC(0)};
+            LF[pr * LP + pidx<N, V>(s0 + v)] = {oka ? TF(R.va[it].v[v]) : TF(0), okb ? TF(R.vb[it].v[v]) : TF(0)};
         }
       } else {
         const int lognlc = A.lognl - 1;
         const int sp = e >> lognlc, pr = e & ((1 << lognlc) - 1);
         const bool ok = 2 * pr < nvalid;
-        L[pr * LP + pidx<N, V>(sp)] = {ok ? TC(R.va[it].v[0]) : TC(0), ok ? TC(R.va[it].v[1]) : TC(0)};
+        LF[pr * LP + pidx<N, V>(sp)] = {ok ? TF(R.va[it].v[0]) : TF(0), ok ? TF(R.va[it].v[1]) : TF(0)};
       }
     }
   };
@@ -475,27 +490,26 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
       for (int e = threadIdx.x; e < total; e += blockDim.x) {
         int s, l;
         tile_coords_p2<CONTIG, N>(e, A.lognl, s, l);
-        const TC v = (l < nvalid) ? TC(src[(size_t)s * A.ss + (size_t)l * A.ls]) : TC(0);
-        Lr[((l >> 1) * LP + pidx<N, V>(s)) * 2 + (l & 1)] = v;
+        const TF v = (l < nvalid) ? TF(src[(size_t)s * A.ss + (size_t)l * A.ls]) : TF(0);
+        LFr[((l >> 1) * LP + pidx<N, V>(s)) * 2 + (l & 1)] = v;
       }
     }
     __syncthreads();
     // the next tile's loads overlap this tile's transforms
     if (A.vec && tile + 1 < tile_end) load_regs(tile + 1, R);
-    fft_line_p2<TC, N, V>(L + c * LP, t, twl);
+    fft_line_p2<TF, N, V>(LF + c * LP, t, twf);
 
     if constexpr (MIDDLE) {
       // Scale the Hartley coefficients by m(q) = 1/(lambda(q) N) and repack them
       // as the next transform's input.  Positions s and N-s of a complex line hold
       // both coefficients of its two real lines at s and N-s, and lambda(s) =
-      // lambda(N-s), so each thread rewrites its own pairs in place.
+      // lambda(N-s), so each thread rewrites its own pairs.
       const int la = 2 * c, lb = 2 * c + 1;
       const TC sa = (la < nvalid) ? s2[outer] + s3[line0 + la] : TC(-1);
       const TC sb = (lb < nvalid) ? s2[outer] + s3[line0 + lb] : TC(-1);
       pow2::CX<TC>* Lc = L + c * LP;
-      for (int sp = t; sp <= N / 2; sp += TPL) {
+      auto scale_pair = [&](int sp, const pow2::CX<TC>& zs, const pow2::CX<TC>& zm) {
         const int sm = (N - sp) & (N - 1);
-        const pow2::CX<TC> zs = Lc[pidx<N, V>(sp)], zm = Lc[pidx<N, V>(sm)];
         const TC ha_s = TC(0.5) * ((zs.x + zm.x) - (zs.y - zm.y));
         const TC hb_s = TC(0.5) * ((zs.y + zm.y) + (zs.x - zm.x));
         const TC ha_m = TC(0.5) * ((zm.x + zs.x) - (zm.y - zs.y));
@@ -506,6 +520,32 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, DhtArgs
         const TC mb = (sb >= TC(0) && lam_b > TC(0)) ? -TC(A.scale) / lam_b : TC(0);
         Lc[pidx<N, V>(sp)] = {ha_s * ma, hb_s * mb};
         Lc[pidx<N, V>(sm)] = {ha_m * ma, hb_m * mb};
+      };
+      if constexpr (F32FWD) {
+        // the FP64 tile overlays the FP32 one: the FP32 pairs of this thread
+        // (s = t + TPL q <= N/2) are read before the barrier, written after it
+        constexpr int NP = N / 2 / TPL + 1;
+        const pow2::CX<TF>* LFc = LF + c * LP;
+        pow2::CX<TF> fs[NP], fm[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const int sp = t + q * TPL;
+          if (sp <= N / 2) {
+            fs[q] = LFc[pidx<N, V>(sp)];
+            fm[q] = LFc[pidx<N, V>((N - sp) & (N - 1))];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const int sp = t + q * TPL;
+          if (sp <= N / 2) scale_pair(sp, {TC(fs[q].x), TC(fs[q].y)}, {TC(fm[q].x), TC(fm[q].y)});
+        }
+      } else {
+        for (int sp = t; sp <= N / 2; sp += TPL) {
+          const pow2::CX<TC> zs = Lc[pidx<N, V>(sp)], zm = Lc[pidx<N, V>((N - sp) & (N - 1))];
+          scale_pair(sp, zs, zm);
+        }
       }
       __syncthreads();
       fft_line_p2<TC, N, V>(L + c * LP, t, twl);
