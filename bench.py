@@ -34,7 +34,7 @@ HBM_PEAK_GBPS = 8000.0
 # Fabric traffic of the fused update kernel per launch and active problem on the 256^3 FP32
 # workload: rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by what they read for the 2 GiB copy
 # kernel, see profiles/k_update_ud_fibres256_f32_traffic.md.  None once the kernel changes.
-K_UPDATE_TRAFFIC_C2 = None
+K_UPDATE_TRAFFIC_C2 = 1.233e9
 
 
 def log(msg):
