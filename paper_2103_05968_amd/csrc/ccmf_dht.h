@@ -384,8 +384,10 @@ struct TileRegs {
 
 // One Hartley pass over a tile of `nl` lines; MIDDLE additionally scales by
 // m(q) and transforms again along the same axis (see k_hartley).  A block walks
-// A.walk consecutive tiles (same outer index, adjacent lines), loading the next
-// tile's samples into registers before it transforms the current one.
+// A.walk tiles at a stride of the grid size (so the blocks running together
+// always work on adjacent tiles, which share the 128-byte lines of a row in
+// L2), loading the next tile's samples into registers before it transforms the
+// current one.
 // With FP32 samples and FP64 compute (the middle pass of FP32 fields) the
 // forward transform runs in FP32 like the other forward passes (tw32: its
 // twiddles) and the coefficients are widened to FP64 before the scaling, so
@@ -424,8 +426,9 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, const p
 
   // XCD-contiguous tiles: neighbouring tiles share the 128-byte lines of a row
   const int ntiles = A.outers * A.tiles_per_outer;
-  const int tile0 = xcd_remap(blockIdx.x, gridDim.x) * A.walk;
-  const int tile_end = min(tile0 + A.walk, ntiles);
+  const int tile0 = xcd_remap(blockIdx.x, gridDim.x);
+  const int tstride = (int)gridDim.x;  // gridDim.x * A.walk >= ntiles
+  const int tile_end = min(tile0 + A.walk * tstride, ntiles);
 
   auto tile_base = [&](int tile, int& outer, int& line0, int& nvalid) -> size_t {
     outer = tile / A.tiles_per_outer;
@@ -480,7 +483,7 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, const p
 
   RG R;
   if (A.vec && tile0 < tile_end) load_regs(tile0, R);
-  for (int tile = tile0; tile < tile_end; ++tile) {
+  for (int tile = tile0; tile < tile_end; tile += tstride) {
     int outer, line0, nvalid;
     const size_t off = tile_base(tile, outer, line0, nvalid);
     if (A.vec) {
@@ -496,7 +499,7 @@ k_hartley_p2(const TI* in, TO* out, const pow2::CX<TC>* __restrict__ tw, const p
     }
     __syncthreads();
     // the next tile's loads overlap this tile's transforms
-    if (A.vec && tile + 1 < tile_end) load_regs(tile + 1, R);
+    if (A.vec && tile + tstride < tile_end) load_regs(tile + tstride, R);
     fft_line_p2<TF, N, V>(LF + c * LP, t, twf);
 
     if constexpr (MIDDLE) {
