@@ -359,13 +359,15 @@ int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, 
 // bit for bit.  Chosen from per-pass timings of every variant on MI355X at 128,
 // 256 and 512 points: FP64 lines radix-8/4 (variant 1) up to 256 and radix-8 (0)
 // from 512; FP32 lines radix-8/4 below 256 and radix-16/8 (0) from 256; the
-// fused divergence pass radix-4 (2) in FP32 up to 256, else radix-8 (0), and in
-// FP64 radix-8 (0) up to 256, radix-16 (1) from 512.  The diagnostic environment
-// variable CCMF_FFT_VARIANT (0, 1 or 2) overrides it.
+// fused i pass radix-16/8 (0) from 128 (its forward half runs in FP32 for FP32
+// fields); the fused divergence pass radix-4 (2) in FP32 up to 256, else radix-8
+// (0), and in FP64 radix-8 (0) up to 256, radix-16 (1) from 512.  The diagnostic
+// environment variable CCMF_FFT_VARIANT (0, 1 or 2) overrides it.
 int variant_of(int kind, bool fp64, int n) {
   const char* env = std::getenv("CCMF_FFT_VARIANT");
   if (env != nullptr && env[0] >= '0' && env[0] <= '2' && env[1] == '\0') return env[0] - '0';
   if (kind == 5) return fp64 ? (n >= 512 ? 1 : 0) : (n >= 512 ? 0 : 2);
+  if (kind == 2 && n >= 128) return 0;
   if (fp64) return n >= 512 ? 0 : 1;
   return n >= 256 ? 0 : 1;
 }
