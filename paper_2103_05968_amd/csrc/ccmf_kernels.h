@@ -380,7 +380,17 @@ __device__ __forceinline__ void block_sum_rows(const double* __restrict__ rows, 
   __shared__ double red[NT / 64][kNQ];
   double acc = 0.0;
   const int total = nrows * kNQ;
-  for (int e = threadIdx.x; e < total; e += NT) acc += rows[e];
+  // U rows of loads in flight, added in the same order as one row at a time
+  constexpr int U = 16;
+  int e = threadIdx.x;
+  for (; e + (U - 1) * NT < total; e += U * NT) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = rows[e + u * NT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += v[u];
+  }
+  for (; e < total; e += NT) acc += rows[e];
   acc += __shfl_down(acc, 32, 64);
   acc += __shfl_down(acc, 16, 64);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
