@@ -40,6 +40,9 @@
  *  - CCMF_FFT_VARIANT = 0, 1 or 2: forces one register-blocked FFT plan variant
  *    in every power-of-two transform pass instead of the autotuner's choice
  *    (results agree to rounding; used to test each variant).
+ *  - CCMF_TILE_WALK = 1 .. 64: forces the number of tiles each block of a
+ *    power-of-two transform pass walks instead of the autotuner's choice (results
+ *    are bit-identical; used to test the walk).
  */
 #ifndef CCMF_H_
 #define CCMF_H_

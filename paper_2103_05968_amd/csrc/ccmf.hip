@@ -330,6 +330,10 @@ int launch_p2v(ccmf_plan_s* p, const TI* in, TO* out, int64_t count, DhtArgs A, 
   // the arithmetic of a tile does not depend on it
   A.outers = outers;
   A.walk = (kind >= 0 && kind < 5 && p->walk_hint[kind] > 0) ? p->walk_hint[kind] : 1;
+  if (const char* env = std::getenv("CCMF_TILE_WALK")) {  // diagnostic override (tests)
+    const int w = std::atoi(env);
+    if (w >= 1 && w <= 64) A.walk = w;
+  }
   const int ntiles = outers * A.tiles_per_outer;
   dim3 grid((unsigned)((ntiles + A.walk - 1) / A.walk), (unsigned)count);
   dim3 block((unsigned)(nlc * TPL));

@@ -316,6 +316,40 @@ def test_not_converged_is_reported():
         p.solve([(1, 0, 0)], tol=1e-12, max_iter=7, raise_not_converged=True)
 
 
+@pytest.mark.parametrize("walk", ["2", "3"])
+def test_tile_walk(walk, rng, monkeypatch):
+    """Transform passes with each block walking several tiles (forced through the
+    diagnostic CCMF_TILE_WALK; the autotuner picks the walk by time, so small cases
+    may never take it): ragged last tiles (24 and 6 lines per outer index), a last
+    walk shorter than the others, and odd line counts (no vector loads).  Results
+    must equal the single-tile walk bit for bit and match numpy and the oracle."""
+    banner(f"tile walk {walk}")
+    for dims in [(32, 64, 24), (16, 32, 6), (16, 32, 5), (64, 16, 32)]:
+        for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 2e-5)):
+            x = rng.standard_normal((2,) + dims)
+            xt = torch.as_tensor(x, dtype=dtype, device=DEV)
+            monkeypatch.setenv("CCMF_TILE_WALK", "1")
+            p1 = plan_of(np.ones(dims), dtype)
+            one = [p1.hartley_axis(xt, axis) for axis in range(3)] + [p1.laplace_pinv(xt)]
+            monkeypatch.setenv("CCMF_TILE_WALK", walk)
+            p = plan_of(np.ones(dims), dtype)
+            for axis in range(3):
+                got = p.hartley_axis(xt, axis)
+                assert torch.equal(got, one[axis]), (dims, axis)
+                want = dht_axis_np(x, axis + 1)
+                got = got.double().cpu().numpy()
+                assert np.abs(got - want).max() <= tol * np.abs(want).max() * 8, (dims, axis)
+            got = p.laplace_pinv(xt)
+            assert torch.equal(got, one[3]), dims
+            want = O.laplace_pinv(x[0])
+            assert np.abs(got[0].double().cpu().numpy() - want).max() <= 5 * tol * np.abs(want).max(), dims
+        gamma = M.boolean_spheres(dims, 2.0, 0.2, 5.0, 1.0, seed=3)
+        res = plan_of(gamma).solve([(0.48, 0.6, 0.64)], tol=1e-300, max_iter=12, autotune=False, want_phi=True)
+        ora = O.admm_solve(gamma, (0.48, 0.6, 0.64), tol=1e-300, max_iter=12)
+        assert abs(res.geff[0, 0] - ora.geff) <= 1e-10 * ora.geff, dims
+        assert np.abs(res.phi[0, 0].cpu().numpy() - ora.phi).max() <= 1e-9 * np.abs(ora.phi).max(), dims
+
+
 @pytest.mark.parametrize("variant", ["0", "1", "2"])
 def test_fft_plan_variants(variant, rng, monkeypatch):
     """Every register-blocked FFT plan variant (forced through the diagnostic
